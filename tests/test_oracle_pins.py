@@ -1,0 +1,321 @@
+"""Pins of the CPU oracle against facts it does not compute itself: textbook
+matrix identities, a Kronecker brute force, closed forms (GHZ, QFT of a basis
+state, product states), a library FFT, exact exponentials, published
+known-answer vectors, and the delta-t^4 Trotter law of Sec. 3.5.
+
+Each pin is chosen so that a plausible mistake (a transposed operand, a wrong
+bit order, a dropped term, a wrong sign) fails at least one of them.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import qsynth
+from oracle import adiabatic, circuits, gates, gradients, observables, sampling, statevec
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------- gates
+@pytest.mark.parametrize("p", ["X", "Y", "Z"])
+def test_rotations_are_pauli_exponentials(p):
+    # R_P(theta) = exp(-i theta P / 2), by scipy's matrix exponential
+    for th in (0.3, 1.7, -2.9):
+        assert np.allclose(gates.matrix("R" + p, th), sla.expm(-0.5j * th * gates.PAULI[p]), atol=1e-14)
+
+
+def test_named_gate_identities():
+    H, X, Y, Z = (gates.matrix(k) for k in "HXYZ")
+    assert np.allclose(H @ H, np.eye(2))
+    assert np.allclose(H @ Z @ H, X)
+    assert np.allclose(X @ Y, 1j * Z)
+    S, T = gates.matrix("S"), gates.matrix("T")
+    assert np.allclose(T @ T, S) and np.allclose(S @ S, Z)
+    assert np.allclose(gates.matrix("U1", np.pi), Z)
+    # RZ is U1 up to a global phase
+    th = 0.77
+    assert np.allclose(gates.matrix("RZ", th), np.exp(-0.5j * th) * gates.matrix("U1", th))
+    sw = gates.matrix("SWAP")
+    assert np.allclose(sw @ sw, np.eye(4))
+
+
+# --------------------------------------------------------------- bit convention
+def test_big_endian_bit_convention():
+    n = 4
+    # X on qubit 0 of |0000> lands on the most significant bit
+    psi = statevec.apply(statevec.zeros(n), gates.matrix("X"), (0,))
+    assert np.argmax(np.abs(psi)) == 8
+    # CNOT control 0 -> target 3 maps |1000> to |1001>
+    psi = statevec.apply(statevec.basis(n, 8), gates.matrix("X"), (3,), (0,))
+    assert np.argmax(np.abs(psi)) == 9
+    # control not satisfied: unchanged
+    psi = statevec.apply(statevec.basis(n, 1), gates.matrix("X"), (2,), (0,))
+    assert np.argmax(np.abs(psi)) == 1
+    # two-qubit matrix: targets[0] is the MSB of the matrix index.
+    # |01> on (q1=0, q3=1) with M = |10><01| gives |10>
+    M = np.zeros((4, 4), dtype=complex)
+    M[2, 1] = 1
+    M[1, 2] = M[0, 0] = M[3, 3] = 1
+    psi = statevec.apply(statevec.basis(n, 0b0001), M, (1, 3))
+    assert np.argmax(np.abs(psi)) == 0b0100
+
+
+# ------------------------------------------------------------ P1: brute force
+@pytest.mark.parametrize("seed", range(6))
+def test_apply_matches_kronecker_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = 5 + seed % 2
+    psi = qsynth.random_state(n, seed)
+    for g in qsynth.random_mixed(n, 12, seed + 100, max_k=3, max_ctrl=2):
+        U = gates.gate_matrix(g)
+        a = statevec.apply(psi, U, g.targets, g.controls)
+        b = statevec.full_unitary(n, U, g.targets, g.controls) @ psi
+        assert np.allclose(a, b, atol=1e-13), g
+        psi = a
+    del rng
+
+
+def test_circuit_unitary_is_unitary_and_matches_run():
+    n = 5
+    spec = qsynth.random_mixed(n, 25, 7, max_k=3, max_ctrl=2)
+    U = circuits.circuit_unitary(n, spec)
+    assert np.allclose(U.conj().T @ U, np.eye(1 << n), atol=1e-12)
+    psi0 = qsynth.random_state(n, 3)
+    assert np.allclose(U @ psi0, circuits.run(n, spec, psi0), atol=1e-12)
+
+
+# ------------------------------------------------------------- P2: GHZ closed form
+@pytest.mark.parametrize("n", [2, 5, 9, 14])
+def test_ghz_closed_form(n):
+    psi = circuits.run(n, qsynth.ghz(n))
+    exp = np.zeros(1 << n, dtype=complex)
+    exp[0] = exp[-1] = 2 ** -0.5
+    assert np.max(np.abs(psi - exp)) < 1e-14
+
+
+# ------------------------------------------------------------- P3 / P4: QFT
+@pytest.mark.parametrize("n", [1, 3, 6, 10])
+def test_qft_basis_closed_form(n):
+    spec = qsynth.qft(n)
+    assert sum(g.name in ("H", "U1") for g in spec) == n * (n + 1) // 2
+    assert sum(g.name == "SWAP" for g in spec) == n // 2
+    x = qsynth.random_basis_index(n, 11)
+    psi = circuits.run(n, spec, statevec.basis(n, x))
+    exp = circuits.qft_basis_amplitudes(n, x, np.arange(1 << n))
+    assert np.max(np.abs(psi - exp)) < 1e-13
+
+
+@pytest.mark.parametrize("n", [4, 8, 11])
+def test_qft_random_state_matches_fft(n):
+    psi0 = qsynth.random_state(n, n)
+    psi = circuits.run(n, qsynth.qft(n), psi0)
+    assert np.max(np.abs(psi - circuits.qft_via_fft(psi0))) < 1e-13
+
+
+def test_qft_closed_form_exact_at_large_n():
+    # the closed form uses exact modular integer arithmetic: compare with a direct
+    # big-integer evaluation at n = 30 for a few indices
+    n, x = 30, 0x2F0F1234
+    ys = np.array([0, 1, 12345, (1 << 30) - 1, 0x15555555])
+    got = circuits.qft_basis_amplitudes(n, x, ys)
+    for y, g in zip(ys, got):
+        ang = 2 * np.pi * ((int(x) * int(y)) % (1 << n)) / (1 << n)
+        assert abs(g - np.exp(1j * ang) * 2 ** (-n / 2)) < 1e-18
+
+
+# ------------------------------------------------------------- P5: product state
+def test_product_state_closed_form():
+    n = 8
+    rng = np.random.default_rng(5)
+    th, ph = rng.uniform(0, 2 * np.pi, n), rng.uniform(0, 2 * np.pi, n)
+    params = np.stack([th, ph], axis=1)[None]
+    psi = circuits.run(n, qsynth.ry_rz_cz_layers(n, params), params=params.reshape(-1))
+    exp = circuits.product_state_amplitudes(n, th, ph, np.arange(1 << n))
+    assert np.max(np.abs(psi - exp)) < 1e-14
+
+
+# ------------------------------------------------------------- P6 / P7 invariants
+def test_norm_and_inverse():
+    n = 7
+    spec = qsynth.random_mixed(n, 40, 9, max_k=3, max_ctrl=2)
+    psi0 = qsynth.random_state(n, 9)
+    psi = circuits.run(n, spec, psi0)
+    assert abs(observables.norm2(psi) - 1) < 1e-13
+    back = circuits.run(n, circuits.inverse(spec), psi)
+    assert np.max(np.abs(back - psi0)) < 1e-13
+
+
+# ------------------------------------------------------------- P8 expectation
+def test_expectation_closed_forms():
+    n = 6
+    zz = qsynth.zz_chain(n, periodic=False)
+    assert abs(observables.expectation(statevec.zeros(n), zz) - (n - 1)) < 1e-14
+    xs = [(1.0, qsynth.pauli_string(n, {i: "X"})) for i in range(n)]
+    assert abs(observables.expectation(statevec.plus(n), xs) - n) < 1e-13
+    rng = np.random.default_rng(1)
+    th = rng.uniform(0, 2 * np.pi, n)
+    psi = statevec.zeros(n)
+    for q in range(n):
+        psi = statevec.apply(psi, gates.matrix("RY", th[q]), (q,))
+    for q in range(n):
+        ez = observables.expectation(psi, [(1.0, qsynth.pauli_string(n, {q: "Z"}))])
+        ex = observables.expectation(psi, [(1.0, qsynth.pauli_string(n, {q: "X"}))])
+        ey = observables.expectation(psi, [(1.0, qsynth.pauli_string(n, {q: "Y"}))])
+        assert abs(ez - np.cos(th[q])) < 1e-14
+        assert abs(ex - np.sin(th[q])) < 1e-14
+        assert abs(ey) < 1e-14
+    e = observables.expectation(psi, [(1.0, qsynth.pauli_string(n, {1: "Z", 4: "Z"}))])
+    assert abs(e - np.cos(th[1]) * np.cos(th[4])) < 1e-14
+
+
+def test_expectation_matches_dense_matrix():
+    n = 6
+    terms = qsynth.random_pauli_sum(n, 15, 4)
+    psi = qsynth.random_state(n, 4)
+    H = observables.dense_pauli_sum(n, terms)
+    assert np.allclose(H, H.conj().T)
+    assert abs(observables.expectation(psi, terms) - np.vdot(psi, H @ psi)) < 1e-13
+    assert abs(observables.expectation(psi, terms).imag) < 1e-13
+
+
+def test_ising_energy_matches_pauli_sum():
+    n = 6
+    J, h = qsynth.ising_couplings(n, 2)
+    E = observables.ising_energies(J, h)
+    Hd = observables.dense_pauli_sum(n, observables.ising_terms(J, h))
+    assert np.allclose(np.diag(Hd).real, E, atol=1e-13)
+    assert np.allclose(Hd - np.diag(np.diag(Hd)), 0)
+
+
+# ------------------------------------------------------------- P9 sampling
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        assert sampling.philox4x32_10(v[0:4], v[4:6]) == tuple(v[6:10])
+
+
+def test_philox_uniforms_are_uniform():
+    u = sampling.philox_uniforms(12345, 20000)
+    assert np.all((u >= 0) & (u < 1))
+    hist, _ = np.histogram(u, bins=20, range=(0, 1))
+    chi2 = np.sum((hist - 1000.0) ** 2 / 1000.0)
+    assert chi2 < 45  # 19 dof, p ~ 1e-3
+
+
+def test_sampling_prefix_equals_marginal_inverse_cdf():
+    n = 8
+    psi = qsynth.random_state(n, 21)
+    u = np.random.default_rng(3).random(5000)
+    got = sampling.sample(psi, [0, 1, 2], u)
+    pm = sampling.marginal(psi, [0, 1, 2])
+    ref = np.searchsorted(np.cumsum(pm), u * pm.sum(), side="right")
+    assert np.array_equal(got, ref)
+
+
+def test_sampling_matches_traced_out_marginal_statistically():
+    n = 7
+    psi = qsynth.random_state(n, 22)
+    q = [5, 1, 3]
+    u = sampling.philox_uniforms(99, 40000)
+    y = sampling.sample(psi, q, u)
+    p = sampling.marginal(psi, q)
+    cnt = np.bincount(y, minlength=p.size)
+    assert 0.5 * np.sum(np.abs(cnt / cnt.sum() - p)) < 0.02
+    # marginal of a product of |0>/|1> on those qubits is a single outcome
+    psi_b = statevec.basis(n, 0b0100010)  # qubits 1 and 5 set
+    assert np.allclose(sampling.marginal(psi_b, q), np.eye(8)[0b110])
+
+
+def test_sampling_ghz_and_uniform():
+    n = 10
+    psi = circuits.run(n, qsynth.ghz(n))
+    y = sampling.sample(psi, list(range(n)), sampling.philox_uniforms(5, 2000))
+    assert set(np.unique(y)) == {0, (1 << n) - 1}
+    hplus = statevec.plus(n)
+    u = np.random.default_rng(0).random(1000)
+    assert np.array_equal(sampling.sample(hplus, list(range(n)), u), np.floor(u * (1 << n)).astype(int))
+
+
+# ------------------------------------------------------------- P11 Trotter
+def tfim_setup(n):
+    z = observables.spins(n)
+    E = -sum(z[:, i] * z[:, (i + 1) % n] for i in range(n))
+    return E
+
+
+def test_trotter_error_scales_as_dt4():
+    n, T, hx = 10, 1.0, 1.0
+    E = tfim_setup(n)
+    cx = lambda s: (1 - s) + s * hx  # noqa: E731   H1 = -sum(ZZ + h X)
+    infid = []
+    dts = [0.1, 0.05, 0.025, 0.0125]
+    for dt in dts:
+        a = adiabatic.trotter(n, E, T, dt, cx)
+        b = adiabatic.exact_piecewise(n, E, T, dt, cx)
+        infid.append(1 - abs(np.vdot(a, b)) ** 2)
+    slope = np.polyfit(np.log(dts), np.log(infid), 1)[0]
+    assert 3.6 < slope < 4.4, (slope, infid)
+
+
+def test_trotter_j0_factorises():
+    n = 6
+    _, h = qsynth.ising_couplings(n, 3)
+    E = observables.ising_energies(np.zeros((n, n)), h)
+    psi = adiabatic.trotter(n, E, 1.0, 0.05)
+    prod = np.array([1.0 + 0j])
+    for q in range(n):
+        prod = np.kron(prod, adiabatic.single_qubit_trotter(h[q], 1.0, 0.05))
+    assert np.max(np.abs(psi - prod)) < 1e-13
+
+
+def test_trotter_exact_for_commuting_parts():
+    # with E = 0 the plus state is an eigenstate of every RX: only a global phase
+    n = 5
+    psi = adiabatic.trotter(n, np.zeros(1 << n), 1.0, 0.1)
+    assert np.max(np.abs(np.abs(psi) - 2 ** (-n / 2))) < 1e-14
+    phase = psi / statevec.plus(n)
+    assert np.max(np.abs(phase - phase[0])) < 1e-14
+    # total phase: sum over steps of n * (1 - s_k) * dt
+    exp_phase = np.exp(1j * n * sum((1 - (k + 0.5) * 0.1) * 0.1 for k in range(10)))
+    assert abs(phase[0] - exp_phase) < 1e-13
+
+
+def test_adiabatic_energy_bounds_and_ground_state():
+    n = 8
+    J, h = qsynth.ising_couplings(n, 1)
+    E = observables.ising_energies(J, h)
+    psi = adiabatic.trotter(n, E, 10.0, 0.05)
+    e = adiabatic.energy(psi, E)
+    assert E.min() - 1e-12 <= e <= E.max()
+    # a slow sweep ends close to the ground state (adiabatic theorem, Sec. 2.6)
+    assert np.abs(psi[np.argmin(E)]) ** 2 > 0.5
+    # eigh of the dense H1 finds the same ground state
+    w, v = np.linalg.eigh(np.diag(E))
+    assert abs(w[0] - E.min()) < 1e-12 and np.argmax(np.abs(v[:, 0])) == np.argmin(E)
+
+
+# ------------------------------------------------------------- P10 gradients
+def test_gradients_three_routes_agree():
+    n, spec, params, terms = qsynth.gradient_20q(seed=3, n=5, layers=3)
+    E, g_adj = gradients.adjoint(n, spec, params, terms)
+    assert abs(E - gradients.energy(n, spec, params, terms)) < 1e-13
+    g_ps = gradients.parameter_shift(n, spec, params, terms)
+    g_fd = gradients.finite_difference(n, spec, params, terms, h=1e-6)
+    assert np.max(np.abs(g_adj - g_ps)) < 1e-12
+    assert np.max(np.abs(g_adj - g_fd)) < 1e-6
+
+
+def test_adjoint_handles_controlled_rotations():
+    n = 4
+    spec = [qsynth.gate("RY", (0,), theta=0.4, pidx=0), qsynth.gate("H", (1,)),
+            qsynth.gate("RX", (2,), (1,), theta=0.9, pidx=1),
+            qsynth.gate("RZ", (3,), (0, 2), theta=1.3, pidx=2), qsynth.gate("X", (3,), (2,))]
+    params = np.array([0.4, 0.9, 1.3])
+    terms = qsynth.random_pauli_sum(n, 6, 8)
+    _, g_adj = gradients.adjoint(n, spec, params, terms)
+    g_fd = gradients.finite_difference(n, spec, params, terms, h=1e-6)
+    assert np.max(np.abs(g_adj - g_fd)) < 1e-7
