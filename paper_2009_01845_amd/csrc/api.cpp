@@ -1,0 +1,942 @@
+// C ABI of the simulator: handle management, validation, plan upload and
+// the host side of every entry point declared in include/qsim.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/qsim.h"
+#include "kernels.h"
+#include "planner.h"
+
+using namespace qs;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+  qs_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(qs_status c, const std::string& m) { throw Fail{c, m}; }
+
+void hipck(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) fail(QS_E_NOMEM, std::string(what) + ": out of device memory");
+  if (e != hipSuccess) fail(QS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F> qs_status guard(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return QS_OK;
+  } catch (const Fail& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return QS_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return QS_E_INVALID;
+  } catch (...) {
+    g_err = "unknown error";
+    return QS_E_DEVICE;
+  }
+}
+
+// ------------------------------------------------------------------ profiling
+struct ProfEv {
+  int fam;
+  hipEvent_t a, b;
+};
+bool g_prof = false;
+std::vector<ProfEv> g_prof_ev;
+int64_t g_prof_cnt[10] = {0};
+double g_prof_ms[10] = {0};
+
+struct ProfScope {
+  int fam;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int f, hipStream_t st) : fam(f), s(st) {
+    if (!g_prof) return;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!g_prof || !a) return;
+    (void)hipEventRecord(b, s);
+    g_prof_ev.push_back({fam, a, b});
+  }
+};
+
+void prof_collect() {
+  for (auto& e : g_prof_ev) {
+    (void)hipEventSynchronize(e.b);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e.a, e.b);
+    g_prof_cnt[e.fam]++;
+    g_prof_ms[e.fam] += ms;
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  g_prof_ev.clear();
+}
+
+// ---------------------------------------------------------------- buffers
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) {
+      hipck(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    if (b == 0) return;
+    hipck(hipMalloc(&p, b), "hipMalloc");
+    bytes = b;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+  ~DBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+template <typename T> void upload(DBuf& d, const std::vector<T>& v, hipStream_t s) {
+  d.ensure(std::max<size_t>(v.size() * sizeof(T), 16));
+  if (!v.empty()) hipck(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+}
+
+bool g_arch_checked = false;
+void check_device() {
+  if (g_arch_checked) return;
+  int dev = 0;
+  hipck(hipGetDevice(&dev), "hipGetDevice");
+  hipDeviceProp_t pr;
+  hipck(hipGetDeviceProperties(&pr, dev), "hipGetDeviceProperties");
+  if (std::strncmp(pr.gcnArchName, "gfx950", 6) != 0)
+    fail(QS_E_UNSUPPORTED, std::string("this library is built for gfx950, device is ") + pr.gcnArchName);
+  g_arch_checked = true;
+}
+
+// Device copy of a plan.
+struct DevPlanBuf {
+  DBuf ops, mat, dpool, phases, qtab, qang;
+  DevPlan view;
+  bool dbl = false;
+  std::vector<PassGeom> geoms;  // op0 filled in
+  void load(const Plan& p, hipStream_t s) {
+    std::vector<TileOp> all;
+    geoms.clear();
+    for (const Pass& ps : p.passes) {
+      PassGeom g = ps.geom;
+      g.op0 = (int)all.size();
+      g.nops = (int)ps.ops.size();
+      all.insert(all.end(), ps.ops.begin(), ps.ops.end());
+      geoms.push_back(g);
+    }
+    upload(ops, all, s);
+    std::vector<double> m(p.matpool.size() * 2);
+    for (size_t i = 0; i < p.matpool.size(); ++i) {
+      m[2 * i] = p.matpool[i].real();
+      m[2 * i + 1] = p.matpool[i].imag();
+    }
+    upload(mat, m, s);
+    upload(dpool, p.dpool, s);
+    upload(phases, p.phases, s);
+    upload(qang, p.qang, s);
+    dbl = p.dbl;
+    if (dbl) {
+      std::vector<double> q(p.qtab.size() * 2);
+      for (size_t i = 0; i < p.qtab.size(); ++i) {
+        q[2 * i] = p.qtab[i].real();
+        q[2 * i + 1] = p.qtab[i].imag();
+      }
+      upload(qtab, q, s);
+    } else {
+      std::vector<float> q(p.qtab.size() * 2);
+      for (size_t i = 0; i < p.qtab.size(); ++i) {
+        q[2 * i] = (float)p.qtab[i].real();
+        q[2 * i + 1] = (float)p.qtab[i].imag();
+      }
+      upload(qtab, q, s);
+    }
+    view.ops = ops.as<TileOp>();
+    view.mat = mat.as<double>();
+    view.dpool = dpool.as<double>();
+    view.phases = phases.as<PhaseRec>();
+    view.qtab = qtab.p;
+    view.qang = qang.as<double>();
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ handles
+struct qs_state {
+  int n = 0;
+  qs_dtype dt = QS_C64;
+  void* ptr = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  DBuf scratch;         // reductions
+  DBuf scratch2;        // sampling prefix / misc
+  DevPlanBuf single;    // plan of the last qs_apply
+  bool dbl() const { return dt == QS_C128; }
+  size_t bytes() const { return (size_t(1) << n) * (dbl() ? 16 : 8); }
+};
+
+struct qs_circuit {
+  HostCircuit hc;
+  bool planned = false;
+  bool plan_dbl = false;
+  TuneOpts plan_opts;
+  bool dev_ok = false;
+  DevPlanBuf dev;
+  DBuf dparams;
+  DBuf gpart;
+  DBuf gout;
+  std::vector<int> slot_pidx;
+};
+
+struct qs_obs {
+  int n = 0;
+  bool ising = false;
+  std::vector<double> J, h;  // ising form (n*n, n)
+  // Pauli form grouped by flip mask
+  std::vector<uint64_t> flips;
+  std::vector<int> goff;
+  std::vector<PauliTermDev> terms;
+  bool dev_ok = false;
+  DBuf dflips, dgoff, dterms;
+  void to_device(hipStream_t s) {
+    if (dev_ok) return;
+    upload(dflips, flips, s);
+    upload(dgoff, goff, s);
+    upload(dterms, terms, s);
+    dev_ok = true;
+  }
+};
+
+namespace {
+
+void check_state(const qs_state* s) {
+  if (!s) fail(QS_E_INVALID, "null state");
+}
+
+int max_qubits(qs_dtype dt) { return dt == QS_C128 ? QS_MAX_QUBITS_C128 : QS_MAX_QUBITS_C64; }
+
+void check_dtype(qs_dtype dt) {
+  if (dt != QS_C64 && dt != QS_C128) fail(QS_E_INVALID, "dtype must be QS_C64 or QS_C128");
+}
+
+void check_mem(size_t bytes) {
+  const char* cap = std::getenv("QS_MEM_LIMIT_BYTES");
+  if (cap && *cap) {
+    const unsigned long long c = std::strtoull(cap, nullptr, 10);
+    if (bytes > c) fail(QS_E_NOMEM, "state exceeds QS_MEM_LIMIT_BYTES");
+  }
+}
+
+void ensure_plan(qs_circuit* c, bool dbl, hipStream_t s) {
+  if (!c->planned || c->plan_dbl != dbl) {
+    c->hc.plan = plan_circuit(c->hc, c->hc.opts, dbl);
+    c->planned = true;
+    c->plan_dbl = dbl;
+    c->dev_ok = false;
+  }
+  if (!c->dev_ok) {
+    c->dev.load(c->hc.plan, s);
+    c->slot_pidx.assign(c->hc.plan.ngrad_slots, -1);
+    for (const Pass& p : c->hc.plan.passes)
+      for (const TileOp& op : p.ops)
+        if (op.kind == OP_ROT && op.gslot >= 0) c->slot_pidx[op.gslot] = op.pidx;
+    c->dev_ok = true;
+  }
+}
+
+// Run every pass of a device plan on a state (forward) or on two states
+// (adjoint: reversed order, gradient partials).
+void run_passes(const DevPlanBuf& dp, const Plan& plan, bool dbl, void* psi, void* lam, const double* params,
+                const double* scales, double* gpart, hipStream_t s) {
+  const int np = (int)plan.passes.size();
+  for (int k = 0; k < np; ++k) {
+    const int i = lam ? np - 1 - k : k;
+    const Pass& ps = plan.passes[i];
+    if (ps.kind == PASS_PERM) {
+      ProfScope pr(2, s);
+      hipck(launch_perm_pass(dbl, psi, ps.geom, ps.sigma.data(), s), "perm pass");
+      if (lam) hipck(launch_perm_pass(dbl, lam, ps.geom, ps.sigma.data(), s), "perm pass");
+    } else {
+      ProfScope pr(lam ? 7 : 0, s);
+      hipck(launch_tile_pass(dbl, psi, lam, dp.geoms[i], dp.view, params, scales, gpart, s), "tile pass");
+    }
+  }
+}
+
+std::vector<cd> read_matrix(const double* mat, int k) {
+  const int d = 1 << k;
+  std::vector<cd> m(size_t(d) * d);
+  for (int i = 0; i < d * d; ++i) m[i] = cd(mat[2 * i], mat[2 * i + 1]);
+  return m;
+}
+
+Gate make_gate(int n, const double* mat, int k, const int* targets, int nctrl, const int* controls) {
+  if (!mat) fail(QS_E_INVALID, "null matrix");
+  std::string err = validate_gate(n, k, targets, nctrl, controls);
+  if (!err.empty()) fail(QS_E_INVALID, err);
+  Gate g;
+  g.k = k;
+  for (int i = 0; i < k; ++i) g.tq[i] = targets[i];
+  for (int i = 0; i < nctrl; ++i) g.cq.push_back(controls[i]);
+  g.mat = read_matrix(mat, k);
+  for (const cd& v : g.mat)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) fail(QS_E_INVALID, "non-finite matrix entry");
+  return g;
+}
+
+double* scratch_doubles(qs_state* s, size_t count) {
+  s->scratch.ensure(count * sizeof(double));
+  return s->scratch.as<double>();
+}
+
+double download_scalar(const double* dev, hipStream_t s) {
+  double v = 0;
+  hipck(hipMemcpyAsync(&v, dev, sizeof(double), hipMemcpyDeviceToHost, s), "download");
+  hipck(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return v;
+}
+
+// Expectation into dev_out[0] (device), asynchronous.
+void expectation_dev(qs_state* s, qs_obs* o, double* dev_out) {
+  o->to_device(s->stream);
+  const int ng = (int)o->flips.size();
+  double* part = scratch_doubles(s, size_t(ng + 1) * kGridMax + ng + 8);
+  double* slots = part + size_t(ng) * kGridMax;
+  ProfScope pr(5, s->stream);
+  hipck(launch_zero(part, int64_t(ng) * kGridMax, s->stream), "zero");
+  for (int g = 0; g < ng; ++g)
+    hipck(launch_expect_group(s->dbl(), s->ptr, s->n, o->flips[g], o->dterms.as<PauliTermDev>() + o->goff[g],
+                              o->goff[g + 1] - o->goff[g], part + size_t(g) * kGridMax, s->stream),
+          "expectation");
+  hipck(launch_slot_sums(part, ng, kGridMax, slots, s->stream), "slot sums");
+  hipck(launch_final_sum(slots, ng, dev_out, s->stream), "final sum");
+}
+
+qs_obs* make_pauli_obs(int n, int nterms, const double* coeffs, const char* const* strings) {
+  std::map<uint64_t, std::vector<PauliTermDev>> groups;
+  for (int t = 0; t < nterms; ++t) {
+    const char* w = strings[t];
+    if (!w) fail(QS_E_INVALID, "null Pauli string");
+    if ((int)std::strlen(w) != n) fail(QS_E_INVALID, "Pauli string length must equal n");
+    if (!std::isfinite(coeffs[t])) fail(QS_E_INVALID, "non-finite coefficient");
+    uint64_t flip = 0, zy = 0;
+    int ny = 0;
+    for (int q = 0; q < n; ++q) {
+      const uint64_t bit = 1ull << (n - 1 - q);
+      switch (w[q]) {
+        case 'I': break;
+        case 'X': flip |= bit; break;
+        case 'Y': flip |= bit; zy |= bit; ++ny; break;
+        case 'Z': zy |= bit; break;
+        default: fail(QS_E_INVALID, std::string("bad Pauli character '") + w[q] + "'");
+      }
+    }
+    PauliTermDev d;
+    d.zy = zy;
+    d.ny4 = ny & 3;
+    d.pad = 0;
+    d.coeff = coeffs[t];
+    groups[flip].push_back(d);
+  }
+  auto* o = new qs_obs;
+  o->n = n;
+  o->goff.push_back(0);
+  for (auto& kv : groups) {
+    o->flips.push_back(kv.first);
+    o->terms.insert(o->terms.end(), kv.second.begin(), kv.second.end());
+    o->goff.push_back((int)o->terms.size());
+  }
+  return o;
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+const char* qs_version(void) { return "qsim-mi355x 0.1.0 (gfx950)"; }
+const char* qs_last_error(void) { return g_err.c_str(); }
+
+qs_status qs_state_create(int32_t n, qs_dtype dt, void* stream, qs_state** out) {
+  return guard([&] {
+    if (!out) fail(QS_E_INVALID, "null output handle");
+    *out = nullptr;
+    check_dtype(dt);
+    if (n < 1 || n > max_qubits(dt)) fail(QS_E_INVALID, "n out of range");
+    auto s = std::make_unique<qs_state>();
+    s->n = n;
+    s->dt = dt;
+    s->stream = (hipStream_t)stream;
+    check_mem(s->bytes());
+    check_device();
+    size_t fr = 0, tot = 0;
+    hipck(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+    if (s->bytes() > fr) fail(QS_E_NOMEM, "state larger than free device memory");
+    hipck(hipMalloc(&s->ptr, s->bytes()), "hipMalloc(state)");
+    s->owned = true;
+    hipck(launch_set_basis(s->dbl(), s->ptr, n, 0, s->stream), "init");
+    *out = s.release();
+  });
+}
+
+qs_status qs_state_wrap(void* dev_ptr, int32_t n, qs_dtype dt, void* stream, qs_state** out) {
+  return guard([&] {
+    if (!out) fail(QS_E_INVALID, "null output handle");
+    *out = nullptr;
+    check_dtype(dt);
+    if (!dev_ptr) fail(QS_E_INVALID, "null device pointer");
+    if (n < 1 || n > max_qubits(dt)) fail(QS_E_INVALID, "n out of range");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 16) fail(QS_E_INVALID, "device pointer not 16-byte aligned");
+    check_device();
+    auto s = std::make_unique<qs_state>();
+    s->n = n;
+    s->dt = dt;
+    s->ptr = dev_ptr;
+    s->owned = false;
+    s->stream = (hipStream_t)stream;
+    *out = s.release();
+  });
+}
+
+qs_status qs_state_destroy(qs_state* s) {
+  return guard([&] {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    else (void)hipDeviceSynchronize();
+    if (s->owned && s->ptr) (void)hipFree(s->ptr);
+    delete s;
+  });
+}
+
+qs_status qs_state_info(const qs_state* s, int32_t* n, qs_dtype* dt, void** dev_ptr) {
+  return guard([&] {
+    check_state(s);
+    if (n) *n = s->n;
+    if (dt) *dt = s->dt;
+    if (dev_ptr) *dev_ptr = s->ptr;
+  });
+}
+
+qs_status qs_state_set_basis(qs_state* s, uint64_t x) {
+  return guard([&] {
+    check_state(s);
+    if (x >> s->n) fail(QS_E_INVALID, "basis index out of range");
+    hipck(launch_set_basis(s->dbl(), s->ptr, s->n, x, s->stream), "set_basis");
+  });
+}
+
+qs_status qs_state_set_plus(qs_state* s) {
+  return guard([&] {
+    check_state(s);
+    hipck(launch_set_plus(s->dbl(), s->ptr, s->n, s->stream), "set_plus");
+  });
+}
+
+qs_status qs_state_upload(qs_state* s, const void* host_src) {
+  return guard([&] {
+    check_state(s);
+    if (!host_src) fail(QS_E_INVALID, "null host pointer");
+    hipck(hipMemcpyAsync(s->ptr, host_src, s->bytes(), hipMemcpyHostToDevice, s->stream), "upload");
+    hipck(hipStreamSynchronize(s->stream), "sync");
+  });
+}
+
+qs_status qs_state_download(const qs_state* s, void* host_dst) {
+  return guard([&] {
+    check_state(s);
+    if (!host_dst) fail(QS_E_INVALID, "null host pointer");
+    hipck(hipMemcpyAsync(host_dst, s->ptr, s->bytes(), hipMemcpyDeviceToHost, s->stream), "download");
+    hipck(hipStreamSynchronize(s->stream), "sync");
+  });
+}
+
+qs_status qs_state_copy(qs_state* dst, const qs_state* src) {
+  return guard([&] {
+    check_state(dst);
+    check_state(src);
+    if (dst->n != src->n || dst->dt != src->dt) fail(QS_E_STATE, "state shapes differ");
+    hipck(hipMemcpyAsync(dst->ptr, src->ptr, dst->bytes(), hipMemcpyDeviceToDevice, dst->stream), "copy");
+  });
+}
+
+qs_status qs_state_sync(const qs_state* s) {
+  return guard([&] {
+    check_state(s);
+    hipck(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+  });
+}
+
+qs_status qs_gate_matrix(const char* name, double theta, double* out, int32_t* k_out) {
+  return guard([&] {
+    if (!name || !out) fail(QS_E_INVALID, "null argument");
+    std::vector<cd> m;
+    const int k = named_gate(name, theta, m);
+    if (!k) fail(QS_E_INVALID, std::string("unknown gate ") + name);
+    for (size_t i = 0; i < m.size(); ++i) {
+      out[2 * i] = m[i].real();
+      out[2 * i + 1] = m[i].imag();
+    }
+    if (k_out) *k_out = k;
+  });
+}
+
+qs_status qs_apply(qs_state* s, const double* mat, int32_t k, const int32_t* targets, int32_t nctrl,
+                   const int32_t* controls) {
+  return guard([&] {
+    check_state(s);
+    HostCircuit hc;
+    hc.n = s->n;
+    hc.gates.push_back(make_gate(s->n, mat, k, targets, nctrl, controls));
+    Plan p = plan_circuit(hc, TuneOpts{}, s->dbl());
+    s->single.load(p, s->stream);
+    run_passes(s->single, p, s->dbl(), s->ptr, nullptr, nullptr, nullptr, nullptr, s->stream);
+  });
+}
+
+// ---------------------------------------------------------------- circuits
+qs_status qs_circuit_create(int32_t n, qs_circuit** out) {
+  return guard([&] {
+    if (!out) fail(QS_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (n < 1 || n > QS_MAX_QUBITS_C64) fail(QS_E_INVALID, "n out of range");
+    auto c = new qs_circuit;
+    c->hc.n = n;
+    *out = c;
+  });
+}
+
+qs_status qs_circuit_add_gate(qs_circuit* c, const double* mat, int32_t k, const int32_t* targets, int32_t nctrl,
+                              const int32_t* controls) {
+  return guard([&] {
+    if (!c) fail(QS_E_INVALID, "null circuit");
+    c->hc.gates.push_back(make_gate(c->hc.n, mat, k, targets, nctrl, controls));
+    c->planned = false;
+  });
+}
+
+qs_status qs_circuit_add_rot(qs_circuit* c, char pauli, int32_t target, int32_t param_index, int32_t nctrl,
+                             const int32_t* controls) {
+  return guard([&] {
+    if (!c) fail(QS_E_INVALID, "null circuit");
+    if (pauli != 'X' && pauli != 'Y' && pauli != 'Z') fail(QS_E_INVALID, "pauli must be X, Y or Z");
+    if (param_index < 0) fail(QS_E_INVALID, "negative parameter index");
+    std::string err = validate_gate(c->hc.n, 1, &target, nctrl, controls);
+    if (!err.empty()) fail(QS_E_INVALID, err);
+    Gate g;
+    g.k = 1;
+    g.tq[0] = target;
+    for (int i = 0; i < nctrl; ++i) g.cq.push_back(controls[i]);
+    g.is_rot = true;
+    g.pauli = pauli;
+    g.pidx = param_index;
+    c->hc.gates.push_back(g);
+    c->hc.nparams = std::max(c->hc.nparams, param_index + 1);
+    c->planned = false;
+  });
+}
+
+qs_status qs_circuit_compile(qs_circuit* c, const qs_tune* opts) {
+  return guard([&] {
+    if (!c) fail(QS_E_INVALID, "null circuit");
+    TuneOpts o;
+    if (opts) {
+      if (opts->tile_bits != 0 && (opts->tile_bits < 6 || opts->tile_bits > kMaxTileBits))
+        fail(QS_E_INVALID, "tile_bits must be 0 or in [6, 13]");
+      if (opts->fuse_k < 0 || opts->fuse_k > 5) fail(QS_E_INVALID, "fuse_k must be in [0, 5]");
+      if (opts->low_bits < 0 || opts->low_bits > 8) fail(QS_E_INVALID, "low_bits must be in [0, 8]");
+      o.tile_bits = opts->tile_bits;
+      o.fuse_k = opts->fuse_k;
+      o.use_mfma = opts->use_mfma;
+      o.low_bits = opts->low_bits;
+    }
+    c->hc.opts = o;
+    // plan for complex64 now (host only); a complex128 run replans
+    c->hc.plan = plan_circuit(c->hc, o, false);
+    c->planned = true;
+    c->plan_dbl = false;
+    c->dev_ok = false;
+  });
+}
+
+qs_status qs_circuit_run(qs_circuit* c, qs_state* s, const double* params, int32_t params_on_device) {
+  return guard([&] {
+    if (!c) fail(QS_E_INVALID, "null circuit");
+    check_state(s);
+    if (c->hc.n != s->n) fail(QS_E_STATE, "circuit and state sizes differ");
+    if (c->hc.nparams > 0 && !params) fail(QS_E_INVALID, "circuit has parameters but params is null");
+    ensure_plan(c, s->dbl(), s->stream);
+    const double* dpar = nullptr;
+    if (c->hc.nparams > 0) {
+      if (params_on_device) {
+        dpar = params;
+      } else {
+        c->dparams.ensure(sizeof(double) * c->hc.nparams);
+        hipck(hipMemcpyAsync(c->dparams.p, params, sizeof(double) * c->hc.nparams, hipMemcpyHostToDevice,
+                             s->stream),
+              "params upload");
+        dpar = c->dparams.as<double>();
+      }
+    }
+    run_passes(c->dev, c->hc.plan, s->dbl(), s->ptr, nullptr, dpar, nullptr, nullptr, s->stream);
+  });
+}
+
+qs_status qs_circuit_info(const qs_circuit* c, int32_t* ngates, int32_t* npasses, int32_t* nparams) {
+  return guard([&] {
+    if (!c) fail(QS_E_INVALID, "null circuit");
+    if (ngates) *ngates = (int)c->hc.gates.size();
+    if (npasses) *npasses = c->planned ? (int)c->hc.plan.passes.size() : -1;
+    if (nparams) *nparams = c->hc.nparams;
+  });
+}
+
+qs_status qs_circuit_pass_info(const qs_circuit* c, int32_t i, int32_t* kind, int32_t* tile_bits, int32_t* nops) {
+  return guard([&] {
+    if (!c) fail(QS_E_INVALID, "null circuit");
+    if (!c->planned) fail(QS_E_STATE, "circuit not compiled");
+    if (i < 0 || i >= (int)c->hc.plan.passes.size()) fail(QS_E_INVALID, "pass index out of range");
+    const Pass& p = c->hc.plan.passes[i];
+    if (kind) *kind = p.kind;
+    if (tile_bits) *tile_bits = p.geom.m;
+    if (nops) *nops = (int)p.ops.size();
+  });
+}
+
+qs_status qs_circuit_destroy(qs_circuit* c) {
+  return guard([&] {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    delete c;
+  });
+}
+
+// ------------------------------------------------------------- observables
+qs_status qs_pauli_sum_create(int32_t n, int32_t nterms, const double* coeffs, const char* const* strings,
+                              qs_obs** out) {
+  return guard([&] {
+    if (!out) fail(QS_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (n < 1 || n > QS_MAX_QUBITS_C64) fail(QS_E_INVALID, "n out of range");
+    if (nterms < 0) fail(QS_E_INVALID, "negative term count");
+    if (nterms > 0 && (!coeffs || !strings)) fail(QS_E_INVALID, "null terms");
+    *out = make_pauli_obs(n, nterms, coeffs, strings);
+  });
+}
+
+qs_status qs_ising_create(int32_t n, const double* J, const double* h, qs_obs** out) {
+  return guard([&] {
+    if (!out) fail(QS_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (n < 1 || n > QS_MAX_QUBITS_C64) fail(QS_E_INVALID, "n out of range");
+    if (!J || !h) fail(QS_E_INVALID, "null J or h");
+    std::vector<double> co;
+    std::vector<std::string> ws;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) {
+        const double v = J[size_t(i) * n + j];
+        if (!std::isfinite(v)) fail(QS_E_INVALID, "non-finite J");
+        if (v == 0.0) continue;
+        std::string w(n, 'I');
+        w[i] = w[j] = 'Z';
+        co.push_back(v);
+        ws.push_back(w);
+      }
+    for (int i = 0; i < n; ++i) {
+      if (!std::isfinite(h[i])) fail(QS_E_INVALID, "non-finite h");
+      std::string w(n, 'I');
+      w[i] = 'Z';
+      co.push_back(h[i]);
+      ws.push_back(w);
+    }
+    std::vector<const char*> pw;
+    for (auto& w : ws) pw.push_back(w.c_str());
+    qs_obs* o = make_pauli_obs(n, (int)co.size(), co.data(), pw.data());
+    o->ising = true;
+    o->J.assign(J, J + size_t(n) * n);
+    o->h.assign(h, h + n);
+    *out = o;
+  });
+}
+
+qs_status qs_obs_destroy(qs_obs* o) {
+  return guard([&] {
+    if (!o) return;
+    (void)hipDeviceSynchronize();
+    delete o;
+  });
+}
+
+qs_status qs_expectation(const qs_state* cs, const qs_obs* co, double* out) {
+  return guard([&] {
+    check_state(cs);
+    if (!co || !out) fail(QS_E_INVALID, "null argument");
+    auto* s = const_cast<qs_state*>(cs);
+    auto* o = const_cast<qs_obs*>(co);
+    if (o->n != s->n) fail(QS_E_STATE, "observable and state sizes differ");
+    const int ng = (int)o->flips.size();
+    if (ng == 0) {
+      *out = 0.0;
+      return;
+    }
+    double* part = scratch_doubles(s, size_t(ng + 1) * kGridMax + ng + 8);
+    double* res = part + size_t(ng + 1) * kGridMax;  // past the slot sums
+    expectation_dev(s, o, res);
+    *out = download_scalar(res, s->stream);
+  });
+}
+
+qs_status qs_expectation_async(const qs_state* cs, const qs_obs* co, double* dev_out) {
+  return guard([&] {
+    check_state(cs);
+    if (!co || !dev_out) fail(QS_E_INVALID, "null argument");
+    auto* s = const_cast<qs_state*>(cs);
+    auto* o = const_cast<qs_obs*>(co);
+    if (o->n != s->n) fail(QS_E_STATE, "observable and state sizes differ");
+    if (o->flips.empty()) {
+      hipck(launch_zero(dev_out, 1, s->stream), "zero");
+      return;
+    }
+    expectation_dev(s, o, dev_out);
+  });
+}
+
+qs_status qs_norm2(const qs_state* cs, double* out) {
+  return guard([&] {
+    check_state(cs);
+    if (!out) fail(QS_E_INVALID, "null output");
+    auto* s = const_cast<qs_state*>(cs);
+    double* part = scratch_doubles(s, kGridMax + 8);
+    ProfScope pr(5, s->stream);
+    hipck(launch_sumsq(s->dbl(), s->ptr, s->n, part, s->stream), "norm");
+    *out = download_scalar(part + kGridMax, s->stream);
+  });
+}
+
+// ---------------------------------------------------------------- sampling
+qs_status qs_sample(const qs_state* cs, int32_t m, const int32_t* qubits, int64_t shots, uint64_t seed,
+                    const double* uniforms, int64_t* out) {
+  return guard([&] {
+    check_state(cs);
+    auto* s = const_cast<qs_state*>(cs);
+    if (m < 1 || m > s->n || m > 63) fail(QS_E_INVALID, "m must be in [1, min(n, 63)]");
+    if (!qubits) fail(QS_E_INVALID, "null qubits");
+    if (shots < 0) fail(QS_E_INVALID, "negative shots");
+    if (shots > 0 && !out) fail(QS_E_INVALID, "null output");
+    uint64_t seen = 0;
+    std::vector<int> pos(m);
+    for (int i = 0; i < m; ++i) {
+      const int q = qubits[i];
+      if (q < 0 || q >= s->n) fail(QS_E_INVALID, "qubit index out of range");
+      if ((seen >> q) & 1) fail(QS_E_INVALID, "duplicate measured qubit");
+      seen |= 1ull << q;
+      pos[i] = s->n - 1 - q;
+    }
+    if (uniforms)
+      for (int64_t j = 0; j < shots; ++j)
+        if (!(uniforms[j] >= 0.0 && uniforms[j] < 1.0)) fail(QS_E_INVALID, "uniforms must lie in [0, 1)");
+    if (shots == 0) return;
+    const int64_t nb = sample_nblocks(s->n);
+    // layout of scratch2: blocksums[nb] | prefix[nb+1] | uniforms[shots] | out[shots]
+    const size_t need = sizeof(double) * (2 * nb + 1 + (uniforms ? shots : 0)) + sizeof(int64_t) * shots + 64;
+    s->scratch2.ensure(need);
+    double* bs = s->scratch2.as<double>();
+    double* pre = bs + nb;
+    double* du = pre + nb + 1;
+    int64_t* dout = reinterpret_cast<int64_t*>(du + (uniforms ? shots : 0));
+    if (uniforms)
+      hipck(hipMemcpyAsync(du, uniforms, sizeof(double) * shots, hipMemcpyHostToDevice, s->stream), "uniforms");
+    {
+      ProfScope pr(6, s->stream);
+      hipck(launch_sample(s->dbl(), s->ptr, s->n, bs, pre, shots, seed, uniforms ? du : nullptr, pos.data(), m,
+                          dout, s->stream),
+            "sample");
+    }
+    hipck(hipMemcpyAsync(out, dout, sizeof(int64_t) * shots, hipMemcpyDeviceToHost, s->stream), "download");
+    hipck(hipStreamSynchronize(s->stream), "sync");
+  });
+}
+
+// ---------------------------------------------------------------- adiabatic
+qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, int32_t order,
+                           double* energy_out) {
+  return guard([&] {
+    check_state(s);
+    if (!h1 || !h1->ising) fail(QS_E_INVALID, "h1 must be an Ising observable");
+    if (h1->n != s->n) fail(QS_E_STATE, "observable and state sizes differ");
+    if (order != 2) fail(QS_E_UNSUPPORTED, "only the second-order split is implemented");
+    if (!(T > 0) || !(dt > 0) || !std::isfinite(T) || !std::isfinite(dt)) fail(QS_E_INVALID, "T and dt must be > 0");
+    const double kf = T / dt;
+    const int64_t K = (int64_t)std::llround(kf);
+    if (K < 1 || std::fabs(kf - (double)K) > 1e-9 * std::max(1.0, kf)) fail(QS_E_INVALID, "T/dt must be an integer");
+    const int n = s->n;
+    const bool dbl = s->dbl();
+    PhasePoly E = ising_poly(n, h1->J.data(), h1->h.data());
+    Plan step = plan_rx_layer(n, dbl, TuneOpts{}, &E);
+    Plan last = plan_rx_layer(n, dbl, TuneOpts{}, nullptr);
+    DevPlanBuf dstep, dlast;
+    dstep.load(step, s->stream);
+    dlast.load(last, s->stream);
+    // merged RX angles and phase scales
+    std::vector<double> ang(K + 1), scl(K);
+    auto sk = [&](int64_t k) { return (double(k) + 0.5) * dt / T; };
+    for (int64_t k = 0; k <= K; ++k) {
+      double a = 0.0;
+      if (k < K) a += -(1.0 - sk(k)) * dt;
+      if (k > 0) a += -(1.0 - sk(k - 1)) * dt;
+      ang[k] = a;
+    }
+    for (int64_t k = 0; k < K; ++k) scl[k] = -sk(k) * dt;
+    DBuf dang, dscl;
+    upload(dang, ang, s->stream);
+    upload(dscl, scl, s->stream);
+    for (int64_t k = 0; k < K; ++k)
+      run_passes(dstep, step, dbl, s->ptr, nullptr, dang.as<double>() + k, dscl.as<double>() + k, nullptr,
+                 s->stream);
+    run_passes(dlast, last, dbl, s->ptr, nullptr, dang.as<double>() + K, nullptr, nullptr, s->stream);
+    if (energy_out) {
+      auto* o = const_cast<qs_obs*>(h1);
+      const int ng = (int)o->flips.size();
+      double* part = scratch_doubles(s, size_t(ng + 1) * kGridMax + ng + 8);
+      double* res = part + size_t(ng + 1) * kGridMax;
+      expectation_dev(s, o, res);
+      *energy_out = download_scalar(res, s->stream);
+    } else {
+      hipck(hipStreamSynchronize(s->stream), "sync");
+    }
+  });
+}
+
+// ---------------------------------------------------------------- adjoint
+qs_status qs_adjoint(qs_circuit* c, const double* params, const qs_obs* H, qs_state* psi, qs_state* lam,
+                     double* grad_out, double* energy_out) {
+  return guard([&] {
+    if (!c || !H) fail(QS_E_INVALID, "null argument");
+    check_state(psi);
+    check_state(lam);
+    if (psi == lam || psi->ptr == lam->ptr) fail(QS_E_INVALID, "psi and lambda must be distinct states");
+    if (c->hc.n != psi->n || lam->n != psi->n || lam->dt != psi->dt || H->n != psi->n)
+      fail(QS_E_STATE, "circuit, observable and states must have the same n and dtype");
+    if (c->hc.nparams > 0 && (!params || !grad_out)) fail(QS_E_INVALID, "null params or grad_out");
+    for (const Gate& g : c->hc.gates)
+      if (!g.is_rot) {
+        const int d = 1 << g.k;
+        for (int i = 0; i < d; ++i)
+          for (int j = 0; j < d; ++j) {
+            cd acc = 0;
+            for (int r = 0; r < d; ++r) acc += std::conj(g.mat[size_t(r) * d + i]) * g.mat[size_t(r) * d + j];
+            if (std::abs(acc - (i == j ? 1.0 : 0.0)) > 1e-9) fail(QS_E_UNSUPPORTED, "adjoint needs unitary gates");
+          }
+      }
+    hipStream_t st = psi->stream;
+    ensure_plan(c, psi->dbl(), st);
+    auto* o = const_cast<qs_obs*>(H);
+    o->to_device(st);
+    const int np = c->hc.nparams;
+    const double* dpar = nullptr;
+    if (np > 0) {
+      c->dparams.ensure(sizeof(double) * np);
+      hipck(hipMemcpyAsync(c->dparams.p, params, sizeof(double) * np, hipMemcpyHostToDevice, st), "params");
+      dpar = c->dparams.as<double>();
+    }
+    // lambda = H psi ; E = Re <psi|lambda>
+    {
+      ProfScope pr(7, st);
+      hipck(launch_apply_hamiltonian(psi->dbl(), psi->ptr, lam->ptr, psi->n, o->dflips.as<uint64_t>(),
+                                     o->dgoff.as<int>(), (int)o->flips.size(), o->dterms.as<PauliTermDev>(), st),
+            "H psi");
+    }
+    double* part = scratch_doubles(psi, kGridMax + 8);
+    hipck(launch_dot_re(psi->dbl(), psi->ptr, lam->ptr, psi->n, part, st), "energy");
+    double E = 0.0;
+    hipck(hipMemcpyAsync(&E, part + kGridMax, sizeof(double), hipMemcpyDeviceToHost, st), "energy");
+    const int ns = c->hc.plan.ngrad_slots;
+    c->gpart.ensure(sizeof(double) * (size_t(std::max(ns, 1)) * kGridMax));
+    c->gout.ensure(sizeof(double) * std::max(ns, 1));
+    if (ns > 0) hipck(launch_zero(c->gpart.as<double>(), int64_t(ns) * kGridMax, st), "zero");
+    run_passes(c->dev, c->hc.plan, psi->dbl(), psi->ptr, lam->ptr, dpar, nullptr, c->gpart.as<double>(), st);
+    std::vector<double> slots(ns);
+    if (ns > 0) {
+      hipck(launch_slot_sums(c->gpart.as<double>(), ns, kGridMax, c->gout.as<double>(), st), "slot sums");
+      hipck(hipMemcpyAsync(slots.data(), c->gout.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st), "grad");
+    }
+    hipck(hipStreamSynchronize(st), "sync");
+    if (np > 0) {
+      std::fill(grad_out, grad_out + np, 0.0);
+      for (int i = 0; i < ns; ++i)
+        if (c->slot_pidx[i] >= 0) grad_out[c->slot_pidx[i]] += slots[i];
+    }
+    if (energy_out) *energy_out = E;
+  });
+}
+
+// ------------------------------------------------------------------- batch
+qs_status qs_batch_create(int32_t, qs_circuit* const*, const qs_obs* const*, qs_dtype, void*, qs_batch** out) {
+  return guard([&] {
+    if (out) *out = nullptr;
+    fail(QS_E_UNSUPPORTED, "batched execution is not built yet");
+  });
+}
+qs_status qs_batch_run(qs_batch*, const double*, double*, double*) {
+  return guard([&] { fail(QS_E_UNSUPPORTED, "batched execution is not built yet"); });
+}
+qs_status qs_batch_destroy(qs_batch*) {
+  return guard([&] {});
+}
+
+qs_status qs_autotune(qs_circuit* c, qs_state* s, const double*, const char*) {
+  return guard([&] {
+    if (!c) fail(QS_E_INVALID, "null circuit");
+    check_state(s);
+    fail(QS_E_UNSUPPORTED, "autotuner is not built yet");
+  });
+}
+
+// --------------------------------------------------------------- profiling
+qs_status qs_profile_enable(int32_t on) {
+  return guard([&] { g_prof = on != 0; });
+}
+qs_status qs_profile_reset(void) {
+  return guard([&] {
+    prof_collect();
+    for (int i = 0; i < 10; ++i) {
+      g_prof_cnt[i] = 0;
+      g_prof_ms[i] = 0;
+    }
+  });
+}
+qs_status qs_profile_read(int32_t family, int64_t* launches, double* total_ms) {
+  return guard([&] {
+    if (family < 0 || family > 9) fail(QS_E_INVALID, "family out of range");
+    prof_collect();
+    if (launches) *launches = g_prof_cnt[family];
+    if (total_ms) *total_ms = g_prof_ms[family];
+  });
+}
+
+}  // extern "C"

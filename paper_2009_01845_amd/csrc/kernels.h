@@ -1,0 +1,64 @@
+// Launch wrappers of the gfx950 kernels (implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qs_types.h"
+
+namespace qs {
+
+// Device copies of a plan's pools.
+struct DevPlan {
+  const TileOp* ops = nullptr;
+  const double* mat = nullptr;    // complex128 interleaved
+  const double* dpool = nullptr;  // phase polynomials
+  const PhaseRec* phases = nullptr;
+  const void* qtab = nullptr;     // complex table in the state precision
+  const double* qang = nullptr;   // the same table as angles
+};
+
+constexpr int kGridMax = 2048;  // fixed upper bound on streaming grids (deterministic reductions)
+
+int tile_grid(const PassGeom& g);
+
+// One tiled pass.  psi2 != nullptr selects the two-state (adjoint) kernel:
+// ops run in reverse with inverse matrices on psi and psi2, and every
+// trainable rotation writes Im<psi2|Pc P psi> partials to
+// gpart[gslot * kGridMax + block] before being undone.
+hipError_t launch_tile_pass(bool dbl, void* psi, void* psi2, const PassGeom& g, const DevPlan& dp,
+                            const double* params, const double* scales, double* gpart, hipStream_t s);
+hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* tau, hipStream_t s);
+
+hipError_t launch_set_basis(bool dbl, void* psi, int n, uint64_t x, hipStream_t s);
+hipError_t launch_set_plus(bool dbl, void* psi, int n, hipStream_t s);
+
+// Reductions: each writes kGridMax-strided float64 partials; final_sum adds
+// `count` partials in a fixed order into out[0] (device).
+hipError_t launch_sumsq(bool dbl, const void* psi, int n, double* partials, hipStream_t s);
+hipError_t launch_dot_re(bool dbl, const void* a, const void* b, int n, double* partials, hipStream_t s);
+struct PauliTermDev {
+  uint64_t zy;     // index bits carrying Z or Y
+  int32_t ny4;     // number of Y factors mod 4
+  int32_t pad;
+  double coeff;
+};
+hipError_t launch_expect_group(bool dbl, const void* psi, int n, uint64_t flip, const PauliTermDev* terms,
+                               int nterms, double* partials, hipStream_t s);
+// lambda = sum_g sum_t c_t P_t psi over all groups (adjoint seed H psi)
+hipError_t launch_apply_hamiltonian(bool dbl, const void* psi, void* lam, int n, const uint64_t* flips,
+                                    const int* group_off, int ngroups, const PauliTermDev* terms,
+                                    hipStream_t s);
+hipError_t launch_final_sum(const double* partials, int count, double* out, hipStream_t s);
+// out[slot] = sum of partials[slot*kGridMax + b], b < nblocks, for every slot
+hipError_t launch_slot_sums(const double* partials, int nslots, int nblocks, double* out, hipStream_t s);
+
+// Sampling (see qsim.h): block sums, scan, per-shot search.
+hipError_t launch_sample(bool dbl, const void* psi, int n, double* blocksums, double* prefix, int64_t shots,
+                         uint64_t seed, const double* uniforms, const int* pos, int m, int64_t* out,
+                         hipStream_t s);
+// zero `count` doubles with a kernel (graph-capture safe)
+hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
+int sample_nblocks(int n);
+
+}  // namespace qs

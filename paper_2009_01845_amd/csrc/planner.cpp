@@ -1,0 +1,613 @@
+// Host pass planner: turns a gate queue into a short list of passes over the
+// state (paper Sec. 2.4.5 fuses gates into at most 4x4 matrices; here every
+// gate whose targets fit one on-chip tile shares a single HBM read+write).
+//
+//  1. SWAP gates become a relabelling of qubits to index bits; the data is
+//     moved once at the end by at most two involutive bit-permutation passes.
+//  2. Diagonal gates with unit-modulus entries on at most two index bits
+//     (Z, S, T, RZ, U1, CZ, CU1 -- the paper's sparse gates, Sec. 2.3) are
+//     collected into a quadratic phase polynomial theta(x) that is applied
+//     element-wise, deferred until a non-diagonal gate touches one of its bits.
+//  3. The other gates are scheduled greedily, in dependency order, into tiled
+//     passes: the tile bit set T = {0..L-1} U (up to m-L high bits); a gate
+//     joins the open pass when its targets fit in T.
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <stdexcept>
+
+namespace qs {
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+bool is_diag(const std::vector<cd>& m, int dim) {
+  for (int r = 0; r < dim; ++r)
+    for (int c = 0; c < dim; ++c)
+      if (r != c && m[size_t(r) * dim + c] != cd(0, 0)) return false;
+  return true;
+}
+
+bool is_swap(const std::vector<cd>& m) {
+  static const int one[4][4] = {{1, 0, 0, 0}, {0, 0, 1, 0}, {0, 1, 0, 0}, {0, 0, 0, 1}};
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c)
+      if (m[r * 4 + c] != cd(one[r][c], 0)) return false;
+  return true;
+}
+
+std::vector<cd> matmul(const std::vector<cd>& a, const std::vector<cd>& b, int dim) {
+  std::vector<cd> o(size_t(dim) * dim, cd(0, 0));
+  for (int i = 0; i < dim; ++i)
+    for (int k = 0; k < dim; ++k) {
+      cd v = a[size_t(i) * dim + k];
+      if (v == cd(0, 0)) continue;
+      for (int j = 0; j < dim; ++j) o[size_t(i) * dim + j] += v * b[size_t(k) * dim + j];
+    }
+  return o;
+}
+
+std::vector<cd> dagger(const std::vector<cd>& a, int dim) {
+  std::vector<cd> o(size_t(dim) * dim);
+  for (int i = 0; i < dim; ++i)
+    for (int j = 0; j < dim; ++j) o[size_t(j) * dim + i] = std::conj(a[size_t(i) * dim + j]);
+  return o;
+}
+
+enum BKind { BK_DENSE = 0, BK_ROT = 1, BK_PHASE = 2 };
+
+struct Term {  // theta contribution: ang * x_p * x_q (p == q: linear)
+  int p, q;
+  double ang;
+};
+
+struct BitGate {
+  int kind = BK_DENSE;
+  int k = 0;
+  int tb[5] = {0, 0, 0, 0, 0};
+  uint64_t cmask = 0;
+  std::vector<cd> mat;
+  char pauli = 0;
+  int pidx = -1;
+  double cphase = 0.0;
+  std::vector<Term> terms;
+  uint64_t nmask = 0;  // bits where the gate is not diagonal
+  uint64_t dmask = 0;  // bits where it is diagonal (controls, diagonal targets)
+};
+
+// Pending op inside an open pass, in global bit terms.
+struct RawOp {
+  int kind;  // OP_*
+  BitGate g;
+  PhasePoly poly;  // OP_PHASE
+};
+
+}  // namespace
+
+std::string validate_gate(int n, int k, const int* targets, int nctrl, const int* controls) {
+  if (k < 1 || k > 5) return "number of targets must be in [1, 5]";
+  if (nctrl < 0) return "negative number of controls";
+  if (k + nctrl > n) return "targets + controls exceed the number of qubits";
+  if (!targets) return "null targets";
+  if (nctrl > 0 && !controls) return "null controls";
+  uint64_t seen = 0;
+  for (int i = 0; i < k + nctrl; ++i) {
+    int q = i < k ? targets[i] : controls[i - k];
+    if (q < 0 || q >= n) return "qubit index out of range";
+    if ((seen >> q) & 1) return "duplicate qubit among targets and controls";
+    seen |= 1ull << q;
+  }
+  return "";
+}
+
+int named_gate(const std::string& name, double theta, std::vector<cd>& out) {
+  const double c = std::cos(theta / 2), s = std::sin(theta / 2);
+  const double r2 = 1.0 / std::sqrt(2.0);
+  const cd I(0, 1);
+  if (name == "H") { out = {r2, r2, r2, -r2}; return 1; }
+  if (name == "X") { out = {0.0, 1.0, 1.0, 0.0}; return 1; }
+  if (name == "Y") { out = {0.0, -I, I, 0.0}; return 1; }
+  if (name == "Z") { out = {1.0, 0.0, 0.0, -1.0}; return 1; }
+  if (name == "S") { out = {1.0, 0.0, 0.0, I}; return 1; }
+  if (name == "T") { out = {1.0, 0.0, 0.0, std::polar(1.0, M_PI / 4)}; return 1; }
+  if (name == "RX") { out = {c, -I * s, -I * s, c}; return 1; }
+  if (name == "RY") { out = {c, -s, s, c}; return 1; }
+  if (name == "RZ") { out = {std::polar(1.0, -theta / 2), 0.0, 0.0, std::polar(1.0, theta / 2)}; return 1; }
+  if (name == "U1") { out = {1.0, 0.0, 0.0, std::polar(1.0, theta)}; return 1; }
+  if (name == "SWAP") {
+    out.assign(16, 0.0);
+    out[0] = out[6] = out[9] = out[15] = 1.0;
+    return 2;
+  }
+  return 0;
+}
+
+void default_tile(int n, bool dbl, const TuneOpts& o, int* m, int* L) {
+  int mm = o.tile_bits > 0 ? o.tile_bits : (dbl ? 11 : 12);
+  int ll = o.low_bits > 0 ? o.low_bits : (dbl ? 5 : 6);
+  mm = std::min(mm, dbl ? 12 : 13);  // <= 64 KiB of LDS per workgroup
+  mm = std::max(mm, 6);
+  if (mm > n) mm = n;
+  if (ll > mm) ll = mm;
+  if (mm < n && mm - ll < 5) ll = std::max(1, mm - 5);  // room for a 5-qubit gate
+  if (mm - ll > 7) ll = mm - 7;                          // at most 2^7 rows per tile
+  if (ll > 8) ll = 8;
+  *m = mm;
+  *L = ll;
+}
+
+namespace {
+
+// Convert a user gate to index bits under the current relabelling.
+BitGate to_bits(const Gate& g, int n, const std::vector<int>& phys) {
+  BitGate b;
+  b.k = g.k;
+  for (int i = 0; i < g.k; ++i) b.tb[i] = phys[g.tq[i]];
+  for (int q : g.cq) b.cmask |= 1ull << phys[q];
+  b.dmask = b.cmask;
+  if (g.is_rot) {
+    b.kind = BK_ROT;
+    b.pauli = g.pauli;
+    b.pidx = g.pidx;
+    if (g.pauli == 'Z') b.dmask |= 1ull << b.tb[0];
+    else b.nmask |= 1ull << b.tb[0];
+    return b;
+  }
+  const int dim = 1 << g.k;
+  b.mat = g.mat;
+  const bool diag = is_diag(g.mat, dim);
+  uint64_t tmask = 0;
+  for (int i = 0; i < g.k; ++i) tmask |= 1ull << b.tb[i];
+  if (!diag) {
+    b.kind = BK_DENSE;
+    b.nmask = tmask;
+    return b;
+  }
+  b.dmask |= tmask;
+  bool unit = true;
+  for (int i = 0; i < dim; ++i)
+    if (std::abs(std::abs(g.mat[size_t(i) * dim + i]) - 1.0) > 1e-12) unit = false;
+  const int nc = (int)g.cq.size();
+  if (!unit || g.k + nc > 2) {
+    b.kind = BK_DENSE;  // diagonal but not a quadratic phase: applied as a tile op
+    return b;
+  }
+  b.kind = BK_PHASE;
+  auto arg = [&](int i) { return std::arg(g.mat[size_t(i) * dim + i]); };
+  if (g.k == 1 && nc == 0) {
+    int a = b.tb[0];
+    b.cphase += arg(0);
+    b.terms.push_back({a, a, arg(1) - arg(0)});
+  } else if (g.k == 1 && nc == 1) {
+    int a = b.tb[0], cb = __builtin_ctzll(b.cmask);
+    b.terms.push_back({cb, cb, arg(0)});
+    b.terms.push_back({std::min(a, cb), std::max(a, cb), arg(1) - arg(0)});
+  } else {  // k == 2, no controls; matrix index = 2*x_a + x_b
+    int a = b.tb[0], bb = b.tb[1];
+    b.cphase += arg(0);
+    b.terms.push_back({a, a, arg(2) - arg(0)});
+    b.terms.push_back({bb, bb, arg(1) - arg(0)});
+    b.terms.push_back({std::min(a, bb), std::max(a, bb), arg(3) - arg(2) - arg(1) + arg(0)});
+  }
+  return b;
+}
+
+void add_terms(PhasePoly& P, int n, const BitGate& g) {
+  P.c += g.cphase;
+  for (const Term& t : g.terms) {
+    if (t.ang == 0.0) continue;
+    if (t.p == t.q) P.mu[t.p] += t.ang;
+    else {
+      P.lam[size_t(t.p) * n + t.q] += t.ang;
+      P.lam[size_t(t.q) * n + t.p] += t.ang;
+    }
+    P.empty = false;
+  }
+  if (g.cphase != 0.0) P.empty = false;
+}
+
+// Move the terms of P that touch any bit of mask into a new polynomial.
+PhasePoly extract_terms(PhasePoly& P, int n, uint64_t mask, bool with_const) {
+  PhasePoly Q;
+  Q.init(n);
+  if (P.empty) return Q;
+  for (int p = 0; p < n; ++p) {
+    if (!((mask >> p) & 1)) continue;
+    if (P.mu[p] != 0.0) { Q.mu[p] = P.mu[p]; P.mu[p] = 0.0; Q.empty = false; }
+    for (int q = 0; q < n; ++q) {
+      double v = P.lam[size_t(p) * n + q];
+      if (v != 0.0) {
+        Q.lam[size_t(p) * n + q] = v;
+        Q.lam[size_t(q) * n + p] = v;
+        P.lam[size_t(p) * n + q] = 0.0;
+        P.lam[size_t(q) * n + p] = 0.0;
+        Q.empty = false;
+      }
+    }
+  }
+  if (with_const && P.c != 0.0) { Q.c = P.c; P.c = 0.0; Q.empty = false; }
+  bool any = P.c != 0.0;
+  for (double v : P.mu) any |= v != 0.0;
+  if (!any)
+    for (double v : P.lam) if (v != 0.0) { any = true; break; }
+  P.empty = !any;
+  return Q;
+}
+
+double wrap_angle(double a) { return a - kTwoPi * std::nearbyint(a / kTwoPi); }
+
+}  // namespace
+
+TileOp make_phase_op(Plan& plan, const PassGeom& g, const PhasePoly& P, int scale_idx) {
+  const int n = g.n;
+  int pos[kMaxTileBits];
+  for (int b = 0; b < g.L; ++b) pos[b] = b;
+  for (int j = 0; j < g.H; ++j) pos[g.L + j] = g.hbits[j];
+  TileOp op;
+  std::memset(&op, 0, sizeof(op));
+  op.kind = OP_PHASE;
+  op.mat = -1;
+  op.pidx = -1;
+  op.gslot = -1;
+  op.sign = 1;
+  PhaseRec rec;
+  rec.dpool = (int)plan.dpool.size();
+  plan.dpool.push_back(P.c);
+  plan.dpool.insert(plan.dpool.end(), P.mu.begin(), P.mu.end());
+  plan.dpool.insert(plan.dpool.end(), P.lam.begin(), P.lam.end());
+  rec.qtab_off = (int)plan.qtab.size();
+  rec.scale_idx = scale_idx;
+  rec.pad = 0;
+  const int M = 1 << g.m;
+  std::vector<double> ang(M, 0.0);
+  for (int j = 1; j < M; ++j) {  // ang[j] = ang[j without its top bit] + the top bit's terms
+    const int top = 31 - __builtin_clz((unsigned)j);
+    const int rest = j & ~(1 << top);
+    const int pt = pos[top];
+    double a = ang[rest] + P.mu[pt];
+    for (int r2 = rest; r2; r2 &= r2 - 1) a += P.lam[size_t(pt) * n + pos[__builtin_ctz((unsigned)r2)]];
+    ang[j] = a;
+  }
+  for (int j = 0; j < M; ++j) {
+    // unscaled tables are exact phases; scaled ones keep the raw angle
+    const double a = scale_idx < 0 ? wrap_angle(ang[j]) : ang[j];
+    plan.qtab.push_back(std::polar(1.0, a));
+    plan.qang.push_back(a);
+  }
+  op.aux = (int)plan.phases.size();
+  plan.phases.push_back(rec);
+  return op;
+}
+
+PhasePoly ising_poly(int n, const double* J, const double* h) {
+  // E(z) = sum_{i<j} J_ij z_i z_j + sum_i h_i z_i with z = 1 - 2 x, x the bit
+  // of qubit q at index position n-1-q
+  PhasePoly P;
+  P.init(n);
+  for (int i = 0; i < n; ++i) {
+    const int a = n - 1 - i;
+    P.c += h[i];
+    P.mu[a] += -2.0 * h[i];
+    for (int j = i + 1; j < n; ++j) {
+      const double v = J[size_t(i) * n + j];
+      if (v == 0.0) continue;
+      const int b = n - 1 - j;
+      P.c += v;
+      P.mu[a] += -2.0 * v;
+      P.mu[b] += -2.0 * v;
+      P.lam[size_t(a) * n + b] += 4.0 * v;
+      P.lam[size_t(b) * n + a] += 4.0 * v;
+    }
+  }
+  P.empty = false;
+  return P;
+}
+
+namespace {
+
+// Close an open pass: fix the tile bit set, convert ops to tile-local form,
+// build the phase tables.
+void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& hsel,
+                std::vector<RawOp>& raw) {
+  const int n = C.n;
+  // pad the high set with the lowest unused bits: longer contiguous runs
+  for (int b = L; b < n && (int)hsel.size() < m - L; ++b) hsel.insert(b);
+  Pass ps;
+  ps.kind = PASS_TILE;
+  PassGeom& g = ps.geom;
+  g.n = n;
+  g.L = L;
+  g.H = (int)hsel.size();
+  g.m = L + g.H;
+  int i = 0;
+  for (int b : hsel) g.hbits[i++] = b;
+  for (; i < kMaxTileBits; ++i) g.hbits[i] = 0;
+  int local[kMaxQubits];
+  for (int b = 0; b < n; ++b) local[b] = -1;
+  for (int b = 0; b < L; ++b) local[b] = b;
+  for (int j = 0; j < g.H; ++j) local[g.hbits[j]] = L + j;
+  int pos[kMaxTileBits];
+  for (int b = 0; b < L; ++b) pos[b] = b;
+  for (int j = 0; j < g.H; ++j) pos[L + j] = g.hbits[j];
+
+  for (RawOp& r : raw) {
+    TileOp op;
+    std::memset(&op, 0, sizeof(op));
+    op.mat = -1;
+    op.pidx = -1;
+    op.aux = -1;
+    op.gslot = -1;
+    op.sign = 1;
+    op.kind = r.kind;
+    if (r.kind == OP_PHASE) {
+      op = make_phase_op(plan, g, r.poly, -1);
+    } else {
+      const BitGate& bg = r.g;
+      op.k = bg.k;
+      for (int t = 0; t < bg.k; ++t) {
+        if (local[bg.tb[t]] < 0) throw std::runtime_error("planner: target outside tile");
+        op.b[t] = local[bg.tb[t]];
+      }
+      for (uint64_t cm = bg.cmask; cm; cm &= cm - 1) {
+        int b = __builtin_ctzll(cm);
+        if (local[b] >= 0) op.cin |= 1u << local[b];
+        else op.cout |= 1ull << b;
+      }
+      if (r.kind == OP_ROT) {
+        op.pidx = bg.pidx;
+        op.pauli = bg.pauli == 'X' ? 1 : bg.pauli == 'Y' ? 2 : 3;
+        if (bg.pidx >= 0) op.gslot = plan.ngrad_slots++;
+      } else {
+        const int dim = 1 << bg.k;
+        op.mat = (int)plan.matpool.size();
+        plan.matpool.insert(plan.matpool.end(), bg.mat.begin(), bg.mat.end());
+        std::vector<cd> inv = dagger(bg.mat, dim);
+        plan.matpool.insert(plan.matpool.end(), inv.begin(), inv.end());
+      }
+    }
+    ps.ops.push_back(op);
+  }
+  if (!ps.ops.empty()) plan.passes.push_back(ps);
+  raw.clear();
+  hsel.clear();
+}
+
+// Involutive bit-permutation pass: data at bit a moves to bit tau[a].
+void add_perm_pass(Plan& plan, int n, int L, bool dbl, const std::vector<int>& tau) {
+  bool ident = true;
+  for (int a = 0; a < n; ++a) ident &= tau[a] == a;
+  if (ident) return;
+  Pass ps;
+  ps.kind = PASS_PERM;
+  ps.sigma = tau;
+  std::set<int> hs;
+  for (int a = 0; a < L; ++a)
+    if (tau[a] >= L) hs.insert(tau[a]);
+  const int mt = std::min(n, dbl ? 10 : 11);
+  for (int b = L; b < n && L + (int)hs.size() < mt; ++b)
+    if (tau[b] == b) hs.insert(b);
+  PassGeom& g = ps.geom;
+  g.n = n;
+  g.L = L;
+  g.H = (int)hs.size();
+  g.m = L + g.H;
+  int i = 0;
+  for (int b : hs) g.hbits[i++] = b;
+  for (; i < kMaxTileBits; ++i) g.hbits[i] = 0;
+  plan.passes.push_back(ps);
+}
+
+}  // namespace
+
+Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
+  const int n = C.n;
+  Plan plan;
+  plan.n = n;
+  plan.dbl = dbl;
+  plan.nparams = C.nparams;
+  plan.ngates = (int)C.gates.size();
+  int m, L;
+  default_tile(n, dbl, opts, &m, &L);
+  const int Hmax = m - L;
+
+  // 1. relabel SWAPs, convert to index bits
+  std::vector<int> phys(n);
+  for (int q = 0; q < n; ++q) phys[q] = n - 1 - q;
+  std::vector<BitGate> bg;
+  bg.reserve(C.gates.size());
+  for (const Gate& g : C.gates) {
+    if (!g.is_rot && g.k == 2 && g.cq.empty() && is_swap(g.mat)) {
+      std::swap(phys[g.tq[0]], phys[g.tq[1]]);
+      continue;
+    }
+    bg.push_back(to_bits(g, n, phys));
+  }
+  const int G = (int)bg.size();
+
+  // 2. dependency graph: two gates commute on a shared bit only when both act
+  //    diagonally there (controls, diagonal gates, Z rotations)
+  std::vector<std::vector<int>> succ(G);
+  std::vector<int> indeg(G, 0);
+  {
+    std::vector<int> lastN(n, -1);
+    std::vector<std::vector<int>> dsince(n);
+    std::vector<int> mark(G, -1);
+    for (int g = 0; g < G; ++g) {
+      auto edge = [&](int from) {
+        if (from < 0 || mark[from] == g) return;
+        mark[from] = g;
+        succ[from].push_back(g);
+        indeg[g]++;
+      };
+      uint64_t all = bg[g].nmask | bg[g].dmask;
+      for (uint64_t t = all; t; t &= t - 1) {
+        int b = __builtin_ctzll(t);
+        edge(lastN[b]);
+        if ((bg[g].nmask >> b) & 1)
+          for (int d : dsince[b]) edge(d);
+      }
+      for (uint64_t t = all; t; t &= t - 1) {
+        int b = __builtin_ctzll(t);
+        if ((bg[g].nmask >> b) & 1) {
+          lastN[b] = g;
+          dsince[b].clear();
+        } else {
+          dsince[b].push_back(g);
+        }
+      }
+    }
+  }
+
+  // 3. greedy list scheduling into tiled passes
+  std::set<int> ready;
+  for (int g = 0; g < G; ++g)
+    if (indeg[g] == 0) ready.insert(g);
+  PhasePoly P;
+  P.init(n);
+  std::set<int> hsel;
+  std::vector<RawOp> raw;
+  int scheduled = 0;
+  const uint64_t lowmask = L >= 64 ? ~0ull : ((1ull << L) - 1);
+  const bool fuse1 = opts.fuse_k != 1;
+
+  auto finish = [&](int g, std::set<int>::iterator& it) {
+    it = ready.erase(it);
+    ++scheduled;
+    for (int s : succ[g])
+      if (--indeg[s] == 0) ready.insert(s);
+  };
+
+  while (scheduled < G) {
+    bool progress = true;
+    int placed = 0;
+    while (progress) {
+      progress = false;
+      for (auto it = ready.begin(); it != ready.end();) {
+        const int g = *it;
+        BitGate& b = bg[g];
+        if (b.kind == BK_PHASE) {
+          add_terms(P, n, b);
+          finish(g, it);
+          progress = true;
+          ++placed;
+          continue;
+        }
+        std::vector<int> need;
+        for (int t = 0; t < b.k; ++t) {
+          int bit = b.tb[t];
+          if (!((lowmask >> bit) & 1) && !hsel.count(bit)) need.push_back(bit);
+        }
+        if ((int)(hsel.size() + need.size()) > Hmax) {
+          ++it;
+          continue;
+        }
+        for (int bit : need) hsel.insert(bit);
+        if (b.nmask) {
+          PhasePoly Q = extract_terms(P, n, b.nmask, false);
+          if (!Q.empty) {
+            RawOp ro;
+            ro.kind = OP_PHASE;
+            ro.poly = std::move(Q);
+            raw.push_back(std::move(ro));
+          }
+        }
+        const int kind = b.kind == BK_ROT ? OP_ROT : (b.k == 1 ? OP_DENSE1 : b.k == 2 ? OP_DENSE2 : OP_DENSEK);
+        bool merged = false;
+        if (fuse1 && kind == OP_DENSE1 && !raw.empty()) {
+          RawOp& last = raw.back();
+          if (last.kind == OP_DENSE1 && last.g.tb[0] == b.tb[0] && last.g.cmask == b.cmask) {
+            last.g.mat = matmul(b.mat, last.g.mat, 2);
+            merged = true;
+          }
+        }
+        if (!merged) {
+          RawOp ro;
+          ro.kind = kind;
+          ro.g = b;
+          raw.push_back(std::move(ro));
+        }
+        finish(g, it);
+        progress = true;
+        ++placed;
+      }
+    }
+    if (scheduled == G && !P.empty) {
+      PhasePoly Q = extract_terms(P, n, ~0ull, true);
+      if (!Q.empty) {
+        RawOp ro;
+        ro.kind = OP_PHASE;
+        ro.poly = std::move(Q);
+        raw.push_back(std::move(ro));
+      }
+    }
+    if (placed == 0 && raw.empty()) throw std::runtime_error("planner: no gate fits a tile");
+    close_pass(plan, C, m, L, hsel, raw);
+  }
+  if (!P.empty) {  // only reachable for an all-diagonal remainder after the loop
+    PhasePoly Q = extract_terms(P, n, ~0ull, true);
+    if (!Q.empty) {
+      RawOp ro;
+      ro.kind = OP_PHASE;
+      ro.poly = std::move(Q);
+      raw.push_back(std::move(ro));
+      close_pass(plan, C, m, L, hsel, raw);
+    }
+  }
+
+  // 4. restore the qubit order: sigma[phys[q]] = n-1-q, as two involutions
+  std::vector<int> sigma(n);
+  bool ident = true;
+  for (int q = 0; q < n; ++q) {
+    sigma[phys[q]] = n - 1 - q;
+    ident &= phys[q] == n - 1 - q;
+  }
+  if (!ident) {
+    std::vector<int> t1(n), t2(n);
+    for (int a = 0; a < n; ++a) t1[a] = t2[a] = a;
+    std::vector<bool> seen(n, false);
+    for (int a0 = 0; a0 < n; ++a0) {
+      if (seen[a0]) continue;
+      std::vector<int> cyc;
+      for (int a = a0; !seen[a]; a = sigma[a]) {
+        seen[a] = true;
+        cyc.push_back(a);
+      }
+      const int len = (int)cyc.size();
+      for (int i = 0; i < len; ++i) {
+        t1[cyc[i]] = cyc[((-i) % len + len) % len];
+        t2[cyc[i]] = cyc[((1 - i) % len + len) % len];
+      }
+    }
+    int Lp = std::min(L, n);
+    add_perm_pass(plan, n, Lp, dbl, t1);
+    add_perm_pass(plan, n, Lp, dbl, t2);
+  }
+  return plan;
+}
+
+Plan plan_rx_layer(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly) {
+  HostCircuit hc;
+  hc.n = n;
+  hc.nparams = 1;
+  for (int q = 0; q < n; ++q) {
+    Gate g;
+    g.k = 1;
+    g.tq[0] = q;
+    g.is_rot = true;
+    g.pauli = 'X';
+    g.pidx = 0;
+    hc.gates.push_back(g);
+  }
+  Plan p = plan_circuit(hc, opts, dbl);
+  if (poly) {
+    Pass& last = p.passes.back();
+    last.ops.push_back(make_phase_op(p, last.geom, *poly, 0));
+  }
+  return p;
+}
+
+}  // namespace qs

@@ -1,0 +1,93 @@
+// Host-side circuit representation and pass planner (no HIP dependency).
+#pragma once
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "qs_types.h"
+
+namespace qs {
+
+using cd = std::complex<double>;
+
+// A user gate in qubit terms (qubit q <-> index bit n-1-q).
+struct Gate {
+  int k = 0;
+  int tq[5] = {0, 0, 0, 0, 0};
+  std::vector<int> cq;
+  bool is_rot = false;
+  char pauli = 0;
+  int pidx = -1;
+  std::vector<cd> mat;  // 2^k x 2^k row-major, MAT gates only
+};
+
+struct TuneOpts {
+  int tile_bits = 0;
+  int fuse_k = 0;
+  int use_mfma = -1;
+  int low_bits = 0;
+};
+
+enum PassKind : int { PASS_TILE = 1, PASS_PHASE = 2, PASS_PERM = 3, PASS_MFMA = 4, PASS_DENSE = 5 };
+
+struct Pass {
+  int kind = PASS_TILE;
+  PassGeom geom{};
+  std::vector<TileOp> ops;
+  std::vector<int> sigma;  // PASS_PERM: data at bit a moves to bit sigma[a] (an involution)
+};
+
+// Quadratic phase polynomial over global index bits.
+struct PhasePoly {
+  double c = 0.0;
+  std::vector<double> mu;   // n
+  std::vector<double> lam;  // n*n symmetric, zero diagonal
+  bool empty = true;
+  void init(int n) { mu.assign(n, 0.0); lam.assign(size_t(n) * n, 0.0); c = 0.0; empty = true; }
+};
+
+struct Plan {
+  int n = 0;
+  bool dbl = false;  // state precision the tables were built for
+  std::vector<Pass> passes;
+  std::vector<cd> matpool;       // gate matrices
+  std::vector<double> dpool;     // phase polynomials: c, mu[n], lam[n*n]
+  std::vector<PhaseRec> phases;
+  std::vector<cd> qtab;          // exp(i theta_T(j)) per phase op
+  std::vector<double> qang;      // theta_T(j) per phase op (same offsets as qtab)
+  int nparams = 0;
+  int ngates = 0;
+  int ngrad_slots = 0;           // ops carrying a trainable parameter
+};
+
+// Circuit description kept by the C ABI.
+struct HostCircuit {
+  int n = 0;
+  std::vector<Gate> gates;
+  int nparams = 0;
+  TuneOpts opts;
+  bool compiled = false;
+  Plan plan;
+};
+
+// Validation used by the ABI (returns empty string when fine).
+std::string validate_gate(int n, int k, const int* targets, int nctrl, const int* controls);
+
+// Plan a circuit for a state of the given precision.  Throws std::runtime_error.
+Plan plan_circuit(const HostCircuit& c, const TuneOpts& opts, bool dbl);
+
+// Default tile geometry for n qubits and a precision.
+void default_tile(int n, bool dbl, const TuneOpts& o, int* m, int* L);
+
+// Build an OP_PHASE op (and its tables) for a pass geometry.  scale_idx >= 0
+// multiplies theta by scales[scale_idx] at run time.
+TileOp make_phase_op(Plan& plan, const PassGeom& g, const PhasePoly& P, int scale_idx);
+// Ising energy E(z) as a polynomial in the index bits.
+PhasePoly ising_poly(int n, const double* J, const double* h);
+// RX(params[0]) on every qubit, optionally followed by exp(i scales[0] E(x)).
+Plan plan_rx_layer(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly);
+
+// Named gate matrices (row-major complex); returns k or 0 for an unknown name.
+int named_gate(const std::string& name, double theta, std::vector<cd>& out);
+
+}  // namespace qs

@@ -1,0 +1,67 @@
+// Plain-old-data records shared by the host planner and the HIP kernels.
+// Nothing here includes HIP headers, so the planner compiles as plain C++.
+#pragma once
+#include <cstdint>
+
+namespace qs {
+
+constexpr int kMaxQubits = 35;
+constexpr int kMaxTileBits = 13;
+constexpr int kMaxOpsPerPass = 512;
+constexpr int kThreads = 256;  // workgroup size of the streaming kernels (4 wave64)
+
+// Op kinds inside a tiled pass.  The tile is the set of 2^m amplitudes that
+// share every index bit outside the tile bit set T; T always holds the
+// lowest L index bits so that each row of 2^L amplitudes is contiguous in HBM.
+enum OpKind : int32_t {
+  OP_DENSE1 = 1,  // 2x2 matrix on tile bit b[0]
+  OP_DENSE2 = 2,  // 4x4 matrix on tile bits (b[0] = MSB of the matrix index, b[1])
+  OP_DENSEK = 3,  // 2^k x 2^k matrix, k = 3..5, on tile bits b[0..k-1]
+  OP_ROT = 4,     // exp(-i theta P/2) on tile bit b[0], theta = sign * params[pidx]
+  OP_PHASE = 5,   // multiply by exp(i theta(x)), theta a quadratic polynomial in index bits
+  OP_DIAG = 6,    // multiply by d[bits of x at up to 6 positions] (any diagonal)
+  OP_MFMA = 7,    // 2^k x 2^k matrix (k = 4, 5) applied with matrix-core instructions
+};
+
+struct TileOp {
+  int32_t kind;
+  int32_t k;         // number of target bits
+  int32_t b[5];      // tile-local bit indices of the targets (b[0] = matrix MSB)
+  uint32_t cin;      // control mask over tile-local bits (all must be 1)
+  uint64_t cout;     // control mask over global index bits outside the tile
+  int32_t mat;       // offset (complex entries) into the matrix pool; -1 if none
+  int32_t pidx;      // OP_ROT: parameter index
+  int32_t pauli;     // OP_ROT: 1 = X, 2 = Y, 3 = Z
+  int32_t sign;      // OP_ROT: +1 forward, -1 inverse
+  int32_t aux;       // OP_PHASE: phase record index; OP_DIAG: offset into diag pool
+  int32_t gslot;     // adjoint: gradient slot of this op (-1 if none)
+  int32_t pad[2];
+};
+
+// A quadratic phase polynomial theta(x) = c + sum_p mu_p x_p + sum_{p<q} lam_pq x_p x_q
+// over index bits x_p, prepared for one tile bit set.  Stored in a double pool:
+//   [0]            c
+//   [1 .. n]       mu_p               (global bit p)
+//   [1+n .. n+n*n] lam (n x n, symmetric, zero diagonal)
+// and a complex table qtab[2^m] = exp(i theta_T(j)) of the polynomial restricted
+// to the tile bits (all outside bits zero, constant excluded), in the state's
+// precision, at qtab_off (complex entries) of the phase-table pool.
+struct PhaseRec {
+  int32_t dpool;     // offset of c in the double pool
+  int32_t qtab_off;  // offset in the complex phase-table pool
+  int32_t scale_idx; // -1: scale 1; else theta is multiplied by scales[scale_idx]
+  int32_t pad;
+};
+
+// Per-pass geometry.
+struct PassGeom {
+  int32_t n;            // qubits
+  int32_t m;            // tile bits
+  int32_t L;            // low bits (0..L-1) in the tile
+  int32_t H;            // high tile bits
+  int32_t hbits[kMaxTileBits];  // global positions of the high tile bits, ascending
+  int32_t nops;
+  int32_t op0;          // first op in the op array
+};
+
+}  // namespace qs

@@ -138,6 +138,8 @@ def random_mixed(n: int, count: int, seed: int, max_k: int = 2, max_ctrl: int = 
     out = []
     for _ in range(count):
         name = names[int(rng.integers(0, len(names)))]
+        if name == "SWAP" and n < 2:
+            name = "H"
         if name == "SWAP":
             k = 2
         elif name == "MAT":

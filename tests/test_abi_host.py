@@ -1,0 +1,150 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point that include/qsim.h declares, validates arguments before
+touching the device, and plans circuits into the expected passes."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import qsynth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qsim.h")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2009_01845_amd import _lib, api
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2009_01845_amd import build
+        build.build()
+    return api
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(qs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for must in ["qs_state_create", "qs_apply", "qs_circuit_compile", "qs_circuit_run", "qs_pauli_sum_create",
+                 "qs_expectation", "qs_sample", "qs_adiabatic_run", "qs_adjoint", "qs_batch_run"]:
+        assert must in syms
+
+
+def test_library_exports_every_declared_symbol(api):
+    from paper_2009_01845_amd import _lib
+    L = C.CDLL(_lib.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(L, s)]
+    assert not missing, missing
+    assert set(declared_symbols()) == set(_lib.SIGNATURES), "binding signatures out of sync with the header"
+
+
+def test_version_and_gate_matrices(api):
+    assert "gfx950" in api.version()
+    # the library's named matrices are the textbook ones (pinned against the
+    # oracle's independent definitions, both checked by closed forms)
+    from oracle import gates as og
+    for name in ["H", "X", "Y", "Z", "S", "T", "SWAP"]:
+        assert np.allclose(api.gate_matrix(name), og.matrix(name), atol=1e-15), name
+    for name in ["RX", "RY", "RZ", "U1"]:
+        for th in (0.0, 0.7, -2.3):
+            assert np.allclose(api.gate_matrix(name, th), og.matrix(name, th), atol=1e-15), name
+    with pytest.raises(api.QsError) as e:
+        api.gate_matrix("NOPE")
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("bad", [
+    dict(targets=[0, 0]), dict(targets=[5]), dict(targets=[-1]), dict(targets=[0], controls=[0]),
+    dict(targets=[0, 1, 2, 3, 4, 5]), dict(targets=[1], controls=[2, 2]),
+])
+def test_gate_validation(api, bad):
+    c = api.circuit_create(4)
+    k = len(bad["targets"])
+    with pytest.raises(api.QsError) as e:
+        api.circuit_add_gate(c, np.eye(1 << min(k, 5)), bad["targets"], bad.get("controls", ()))
+    assert e.value.code == -1
+    api.circuit_destroy(c)
+
+
+def test_circuit_and_observable_validation(api):
+    for n in (0, 36, -3):
+        with pytest.raises(api.QsError):
+            api.circuit_create(n)
+    c = api.circuit_create(3)
+    with pytest.raises(api.QsError):
+        api.circuit_add_rot(c, "Q", 0, 0)
+    with pytest.raises(api.QsError):
+        api.circuit_add_rot(c, "X", 0, -1)
+    with pytest.raises(api.QsError):
+        api.circuit_compile(c, tile_bits=40)
+    api.circuit_destroy(c)
+    with pytest.raises(api.QsError):
+        api.pauli_sum_create(3, [(1.0, "XQZ")])
+    with pytest.raises(api.QsError):
+        api.pauli_sum_create(3, [(1.0, "XZ")])
+    o = api.pauli_sum_create(3, [(1.0, "XYZ"), (0.5, "IIZ")])
+    api.obs_destroy(o)
+
+
+def test_null_and_range_checks_do_not_touch_the_device(api):
+    from paper_2009_01845_amd import _lib
+    L = _lib.lib()
+    h = C.c_void_p()
+    assert L.qs_state_create(0, 1, None, C.byref(h)) == -1
+    assert L.qs_state_create(36, 1, None, C.byref(h)) == -1
+    assert L.qs_state_create(10, 7, None, C.byref(h)) == -1
+    assert L.qs_state_create(10, 1, None, None) == -1
+    assert L.qs_state_wrap(None, 10, 1, None, C.byref(h)) == -1
+    assert L.qs_state_wrap(C.c_void_p(8), 10, 1, None, C.byref(h)) == -1  # misaligned
+    assert L.qs_norm2(None, None) == -1
+    assert L.qs_expectation(None, None, None) == -1
+    assert "null" in L.qs_last_error().decode()
+    assert L.qs_state_destroy(None) == 0
+
+
+def test_memory_cap_forces_nomem(api, monkeypatch):
+    from paper_2009_01845_amd import _lib
+    monkeypatch.setenv("QS_MEM_LIMIT_BYTES", "1024")
+    h = C.c_void_p()
+    assert _lib.lib().qs_state_create(20, 1, None, C.byref(h)) == -2
+    assert "QS_MEM_LIMIT_BYTES" in _lib.lib().qs_last_error().decode()
+
+
+# ------------------------------------------------------------ planning (host)
+def test_qft_plan_shape(api):
+    for n, expect_max in [(28, 5), (30, 5)]:
+        c = api.Circuit.from_spec(n, qsynth.qft(n))
+        g, p, _ = c.info()
+        assert g == n * (n + 1) // 2 + n // 2
+        kinds = [k for k, _, _ in c.passes()]
+        assert kinds.count(3) == 1        # the SWAP network is one bit-reversal pass
+        assert p <= expect_max, c.passes()
+
+
+def test_diagonal_only_circuit_is_one_pass(api):
+    n = 20
+    spec = [qsynth.gate("Z", (i + 1,), (i,)) for i in range(n - 1)] + [qsynth.gate("T", (3,)),
+                                                                      qsynth.gate("RZ", (7,), theta=0.4)]
+    c = api.Circuit.from_spec(n, spec)
+    assert c.info()[1] == 1
+
+
+def test_tile_options_change_the_plan(api):
+    n = 26
+    spec = qsynth.random_layers(n, 4, 3)
+    p12 = api.Circuit.from_spec(n, spec, tile_bits=12).info()[1]
+    p8 = api.Circuit.from_spec(n, spec, tile_bits=8, low_bits=3).info()[1]
+    assert p8 > p12
+
+
+def test_swap_relabel_needs_no_pass_when_undone(api):
+    n = 16
+    spec = [qsynth.gate("SWAP", (0, 15)), qsynth.gate("SWAP", (0, 15))]
+    assert api.Circuit.from_spec(n, spec).info()[1] == 0
+    spec = [qsynth.gate("SWAP", (0, 5)), qsynth.gate("SWAP", (5, 9))]  # a 3-cycle: two involutions
+    assert api.Circuit.from_spec(n, spec).info()[1] == 2

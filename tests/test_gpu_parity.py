@@ -1,0 +1,320 @@
+"""Parity of the HIP path with the CPU oracle, element by element, on seeded
+inputs.  Tolerances: max-abs amplitude error 1e-12 (complex128) and 1e-5
+(complex64); complex64 runs are compared with the oracle applied to the
+complex64-rounded input."""
+import numpy as np
+import pytest
+
+import qsynth
+from oracle import adiabatic as oad
+from oracle import circuits as ocirc
+from oracle import gates as ogates
+from oracle import gradients as ograd
+from oracle import observables as oobs
+from oracle import sampling as osamp
+from oracle import statevec as osv
+
+from gpu_util import TOL, banner, gpu_state, maxabs, oracle_input
+
+pytestmark = pytest.mark.gpu
+DTS = ["c64", "c128"]
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2009_01845_amd import api as a
+    return a
+
+
+# ---------------------------------------------------------------- single gates
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 11, 14])
+def test_single_gates(api, dt, n):
+    banner("single gates", dt, n)
+    psi0 = qsynth.random_state(n, 100 + n)
+    st = gpu_state(api, n, dt, psi0)
+    ref = oracle_input(psi0, dt)
+    spec = qsynth.random_mixed(n, 30, 7 + n, max_k=min(n, 5), max_ctrl=min(2, n - 1))
+    worst = 0.0
+    for g in spec:
+        U = ogates.gate_matrix(g)
+        api.apply(st.h, U, g.targets, g.controls)
+        ref = osv.apply(ref, U, g.targets, g.controls)
+        if n <= 6:
+            worst = max(worst, maxabs(st.download(), ref))
+            assert worst < TOL[dt], (g, worst)
+    assert maxabs(st.download(), ref) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_every_bit_position_1q_and_controlled(api, dt):
+    n = 13
+    banner("every bit", dt, n)
+    psi0 = qsynth.random_state(n, 5)
+    st = gpu_state(api, n, dt, psi0)
+    ref = oracle_input(psi0, dt)
+    rng = np.random.default_rng(1)
+    for q in range(n):
+        U = qsynth.haar_unitary(2, rng)
+        api.apply(st.h, U, (q,))
+        ref = osv.apply(ref, U, (q,))
+        c = (q + 5) % n
+        api.apply(st.h, ogates.matrix("RY", 0.3 + q), (q,), (c,))
+        ref = osv.apply(ref, ogates.matrix("RY", 0.3 + q), (q,), (c,))
+    assert maxabs(st.download(), ref) < TOL[dt]
+
+
+# ---------------------------------------------------------------- circuits
+TILES = [dict(), dict(tile_bits=6, low_bits=1), dict(tile_bits=8, low_bits=3), dict(tile_bits=10, low_bits=4),
+         dict(tile_bits=12, low_bits=6), dict(tile_bits=13, low_bits=8)]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("ti", range(len(TILES)))
+def test_random_circuit_tilings(api, dt, ti):
+    opts = dict(TILES[ti])
+    if dt == "c128" and opts.get("tile_bits", 0) > 12:
+        opts["tile_bits"] = 12
+    n = 15
+    banner("random circuit", dt, opts)
+    spec = qsynth.random_mixed(n, 160, 42, max_k=3, max_ctrl=2)
+    psi0 = qsynth.random_state(n, 9)
+    c = api.Circuit.from_spec(n, spec, **opts)
+    st = gpu_state(api, n, dt, psi0)
+    c.run(st)
+    ref = ocirc.run(n, spec, oracle_input(psi0, dt))
+    assert maxabs(st.download(), ref) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_variational_10q_depth20(api, dt):
+    banner("variational 10q", dt)
+    n, spec, params, terms = qsynth.variational_10q(0)
+    c = api.Circuit.from_spec(n, spec)
+    st = gpu_state(api, n, dt)
+    c.run(st, params)
+    ref = ocirc.run(n, spec, None, params)
+    assert maxabs(st.download(), ref) < TOL[dt]
+    H = api.Observable.pauli_sum(n, terms)
+    e = H.expectation(st)
+    assert abs(e - oobs.expectation(ref, terms).real) < (1e-12 if dt == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_qft_random_state_vs_fft(api, dt):
+    n = 18
+    banner("qft fft", dt, n)
+    psi0 = qsynth.random_state(n, 3)
+    c = api.Circuit.from_spec(n, qsynth.qft(n))
+    st = gpu_state(api, n, dt, psi0)
+    c.run(st)
+    assert maxabs(st.download(), ocirc.qft_via_fft(oracle_input(psi0, dt))) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt,n", [("c64", 28), ("c128", 28), ("c64", 30)])
+def test_qft_basis_closed_form_large(api, dt, n):
+    banner("qft basis large", dt, n)
+    import torch
+    x = qsynth.random_basis_index(n, 2024 + n)
+    c = api.Circuit.from_spec(n, qsynth.qft(n))
+    st = api.State(n, dt)
+    st.set_basis(x)
+    c.run(st)
+    rng = np.random.default_rng(0)
+    ys = np.concatenate([[0, 1, (1 << n) - 1, 1 << (n - 1)], rng.integers(0, 1 << n, 200000)]).astype(np.int64)
+    got = st.tensor[torch.from_numpy(ys).cuda()].cpu().numpy()
+    exp = ocirc.qft_basis_amplitudes(n, x, ys.astype(np.uint64))
+    assert maxabs(got, exp) < TOL[dt]
+    assert abs(st.norm2() - 1) < (1e-12 if dt == "c128" else 1e-5)
+    del st
+    torch.cuda.empty_cache()
+
+
+def test_ghz_and_product_state_at_30_qubits(api):
+    import torch
+    n = 30
+    banner("ghz / product 30")
+    st = api.State(n, "c64")
+    api.Circuit.from_spec(n, qsynth.ghz(n)).run(st)
+    rng = np.random.default_rng(1)
+    ys = np.concatenate([[0, (1 << n) - 1], rng.integers(1, (1 << n) - 1, 100000)]).astype(np.int64)
+    got = st.tensor[torch.from_numpy(ys).cuda()].cpu().numpy()
+    exp = np.zeros(ys.size, dtype=complex)
+    exp[0] = exp[1] = 2 ** -0.5
+    assert maxabs(got, exp) < 1e-6
+    # one RY/RZ/CZ layer from |0..0>: closed-form product state
+    th, ph = rng.uniform(0, 2 * np.pi, n), rng.uniform(0, 2 * np.pi, n)
+    params = np.stack([th, ph], axis=1)[None]
+    st.set_basis(0)
+    api.Circuit.from_spec(n, qsynth.ry_rz_cz_layers(n, params)).run(st, params.reshape(-1))
+    got = st.tensor[torch.from_numpy(ys).cuda()].cpu().numpy()
+    exp = ocirc.product_state_amplitudes(n, th, ph, ys)
+    assert maxabs(got, exp) < 1e-5
+    del st
+    torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- observables
+@pytest.mark.parametrize("dt", DTS)
+def test_expectation_and_norm(api, dt):
+    n = 12
+    banner("expectation", dt)
+    psi0 = qsynth.random_state(n, 77)
+    st = gpu_state(api, n, dt, psi0)
+    ref = oracle_input(psi0, dt)
+    terms = qsynth.random_pauli_sum(n, 40, 3)
+    H = api.Observable.pauli_sum(n, terms)
+    tol = 1e-12 if dt == "c128" else 1e-6
+    assert abs(H.expectation(st) - oobs.expectation(ref, terms).real) < tol
+    assert abs(st.norm2() - oobs.norm2(ref)) < tol
+    J, h = qsynth.ising_couplings(n, 4)
+    I = api.Observable.ising(n, J, h)
+    assert abs(I.expectation(st) - float(np.sum(np.abs(ref) ** 2 * oobs.ising_energies(J, h)))) < tol * 10
+
+
+# ---------------------------------------------------------------- sampling
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("shots", [1, 7, 4099])
+def test_sampling_shared_uniforms(api, dt, shots):
+    n = 13
+    banner("sampling", dt, shots)
+    psi0 = qsynth.random_state(n, 8)
+    st = gpu_state(api, n, dt, psi0)
+    ref = oracle_input(psi0, dt)
+    u = np.random.default_rng(shots).random(shots)
+    for qubits in (list(range(n)), [4, 0, 9], [12]):
+        got = api.sample(st.h, qubits, shots, uniforms=u)
+        exp = osamp.sample(ref, qubits, u)
+        bad = np.nonzero(got != exp)[0]
+        if bad.size:
+            # a mismatch is only acceptable at a CDF boundary (summation order)
+            idx = osamp.sample_indices(ref, u[bad])
+            assert np.all(osamp.boundary_distance(ref, u[bad], idx) < 1e-6), bad
+
+
+def test_sampling_philox_seed_mode_matches_oracle_generator(api):
+    n = 12
+    banner("sampling philox")
+    psi0 = qsynth.random_state(n, 2)
+    st = gpu_state(api, n, "c128", psi0)
+    got = api.sample(st.h, list(range(n)), 3000, seed=0xDEADBEEF12345)
+    u = osamp.philox_uniforms(0xDEADBEEF12345, 3000)
+    exp = osamp.sample(psi0, list(range(n)), u)
+    assert np.mean(got == exp) > 0.999
+
+
+def test_sampling_ghz_and_uniform(api):
+    n = 20
+    banner("sampling ghz")
+    st = api.State(n, "c64")
+    api.Circuit.from_spec(n, qsynth.ghz(n)).run(st)
+    y = api.sample(st.h, list(range(n)), 10000, seed=3)
+    assert set(np.unique(y)) <= {0, (1 << n) - 1}
+    assert 0.45 < np.mean(y == 0) < 0.55
+
+
+# ---------------------------------------------------------------- adiabatic
+@pytest.mark.parametrize("dt", DTS)
+def test_adiabatic_trotter_vs_oracle(api, dt):
+    n = 9
+    banner("adiabatic", dt)
+    J, h = qsynth.ising_couplings(n, 5)
+    E = oobs.ising_energies(J, h)
+    ref = oad.trotter(n, E, 2.0, 0.05)
+    st = api.State(n, dt)
+    st.set_plus()
+    I = api.Observable.ising(n, J, h)
+    e = api.adiabatic_run(st.h, I.h, 2.0, 0.05)
+    assert maxabs(st.download(), ref) < (1e-11 if dt == "c128" else 2e-5)
+    assert abs(e - oad.energy(ref, E)) < (1e-10 if dt == "c128" else 1e-4)
+
+
+def test_adiabatic_j0_factorised_20q(api):
+    n = 20
+    banner("adiabatic J=0", n)
+    _, h = qsynth.ising_couplings(n, 6)
+    T, dt = 1.0, 0.01
+    st = api.State(n, "c128")
+    st.set_plus()
+    I = api.Observable.ising(n, np.zeros((n, n)), h)
+    api.adiabatic_run(st.h, I.h, T, dt)
+    got = st.download()
+    prod = np.array([1.0 + 0j])
+    for q in range(n):
+        prod = np.kron(prod, oad.single_qubit_trotter(h[q], T, dt))
+    assert maxabs(got, prod) < 1e-12
+
+
+# ---------------------------------------------------------------- adjoint
+@pytest.mark.parametrize("dt", DTS)
+def test_adjoint_gradient_small(api, dt):
+    n = 8
+    banner("adjoint small", dt)
+    spec = [qsynth.gate("RY", (q,), theta=0.0, pidx=q) for q in range(n)]
+    spec += [qsynth.gate("H", (2,)), qsynth.gate("RX", (3,), (1,), pidx=n), qsynth.gate("X", (5,), (0,))]
+    spec += [qsynth.gate("RZ", (6,), (2, 4), pidx=n + 1), qsynth.gate("U1", (7,), (3,), theta=0.8)]
+    spec += [qsynth.gate("RX", (q,), pidx=n + 2 + q) for q in range(n)]
+    spec += [qsynth.gate("SWAP", (0, 7)), qsynth.gate("RY", (0,), pidx=2 * n + 2)]
+    params = np.random.default_rng(4).uniform(0, 2 * np.pi, 2 * n + 3)
+    terms = qsynth.random_pauli_sum(n, 12, 6)
+    E_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+    c = api.Circuit.from_spec(n, spec)
+    psi = api.State(n, dt)
+    c.run(psi, params)
+    lam = api.State(n, dt)
+    H = api.Observable.pauli_sum(n, terms)
+    E, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+    tol = 1e-10 if dt == "c128" else 1e-4
+    assert abs(E - E_ref) < tol
+    assert np.max(np.abs(g - g_ref)) < tol
+    # psi was walked back to the input |0..0>
+    back = psi.download()
+    assert abs(back[0] - 1) < (1e-10 if dt == "c128" else 1e-4)
+
+
+def test_adjoint_variational_12q_vs_parameter_shift(api):
+    n, spec, params, terms = qsynth.gradient_20q(seed=1, n=12, layers=4)
+    banner("adjoint 12q")
+    g_ps = ograd.parameter_shift(n, spec, params, terms)
+    c = api.Circuit.from_spec(n, spec)
+    for dt, tol in (("c128", 1e-10), ("c64", 1e-4)):
+        psi = api.State(n, dt)
+        c.run(psi, params)
+        lam = api.State(n, dt)
+        H = api.Observable.pauli_sum(n, terms)
+        _, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+        assert np.max(np.abs(g - g_ps)) < tol, dt
+
+
+def test_autograd_energy(api):
+    import torch
+    from paper_2009_01845_amd.autograd import energy
+    n, spec, params, terms = qsynth.gradient_20q(seed=2, n=6, layers=2)
+    banner("autograd")
+    c = api.Circuit.from_spec(n, spec)
+    H = api.Observable.pauli_sum(n, terms)
+    p = torch.tensor(params, requires_grad=True)
+    E = energy(p, c, H, "c128")
+    E.backward()
+    E_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+    assert abs(E.item() - E_ref) < 1e-12
+    assert np.max(np.abs(p.grad.numpy() - g_ref)) < 1e-10
+
+
+# ---------------------------------------------------------------- determinism
+def test_bitwise_determinism(api):
+    n = 16
+    banner("determinism")
+    spec = qsynth.random_mixed(n, 100, 5, max_k=2, max_ctrl=1)
+    c = api.Circuit.from_spec(n, spec)
+    psi0 = qsynth.random_state(n, 1)
+    H = api.Observable.pauli_sum(n, qsynth.random_pauli_sum(n, 10, 1))
+    outs = []
+    for _ in range(2):
+        st = gpu_state(api, n, "c64", psi0)
+        c.run(st)
+        outs.append((st.download(), H.expectation(st), st.norm2()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1] and outs[0][2] == outs[1][2]
