@@ -28,6 +28,10 @@ FLAGS = [
     "-Wall",
     "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep the register-slot switch cases apart: sinking their common tails
+    # into one block turns register-array accesses into pointer selects,
+    # which forces the arrays into scratch memory
+    "-mllvm", "-simplifycfg-sink-common=false",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -136,7 +136,8 @@ void check_device() {
 
 // Device copy of a plan.
 struct DevPlanBuf {
-  DBuf ops, mat, dpool, phases, qtab, qang;
+  DBuf ops, mat, dpool, phases, qtab, qang, stages, phlist, btab, matc;
+  bool has_rot = false;
   DevPlan view;
   bool dbl = false;
   std::vector<PassGeom> geoms;  // op0 filled in
@@ -157,9 +158,20 @@ struct DevPlanBuf {
       m[2 * i + 1] = p.matpool[i].imag();
     }
     upload(mat, m, s);
+    if (p.dbl) {
+      upload(matc, m, s);
+    } else {
+      std::vector<float> mf(m.begin(), m.end());
+      upload(matc, mf, s);
+    }
+    has_rot = false;
+    for (const TileOp& op : all) has_rot |= op.kind == OP_ROT;
     upload(dpool, p.dpool, s);
     upload(phases, p.phases, s);
     upload(qang, p.qang, s);
+    upload(stages, p.stages, s);
+    upload(phlist, p.phlist, s);
+    upload(btab, p.btab, s);
     dbl = p.dbl;
     if (dbl) {
       std::vector<double> q(p.qtab.size() * 2);
@@ -182,6 +194,11 @@ struct DevPlanBuf {
     view.phases = phases.as<PhaseRec>();
     view.qtab = qtab.p;
     view.qang = qang.as<double>();
+    view.stages = stages.as<StageRec>();
+    view.phlist = phlist.as<int32_t>();
+    view.btab = btab.as<double>();
+    view.matc = matc.p;
+    view.nops_total = (int)all.size();
   }
 };
 
@@ -275,6 +292,7 @@ void ensure_plan(qs_circuit* c, bool dbl, hipStream_t s) {
 void run_passes(const DevPlanBuf& dp, const Plan& plan, bool dbl, void* psi, void* lam, const double* params,
                 const double* scales, double* gpart, hipStream_t s) {
   const int np = (int)plan.passes.size();
+  if (dp.has_rot && params) hipck(launch_rot_mats(dbl, dp.view, params, s), "rotation matrices");
   for (int k = 0; k < np; ++k) {
     const int i = lam ? np - 1 - k : k;
     const Pass& ps = plan.passes[i];
@@ -334,7 +352,7 @@ void expectation_dev(qs_state* s, qs_obs* o, double* dev_out) {
     hipck(launch_expect_group(s->dbl(), s->ptr, s->n, o->flips[g], o->dterms.as<PauliTermDev>() + o->goff[g],
                               o->goff[g + 1] - o->goff[g], part + size_t(g) * kGridMax, s->stream),
           "expectation");
-  hipck(launch_slot_sums(part, ng, kGridMax, slots, s->stream), "slot sums");
+  hipck(launch_slot_sums(part, ng, kGridMax, kGridMax, slots, s->stream), "slot sums");
   hipck(launch_final_sum(slots, ng, dev_out, s->stream), "final sum");
 }
 
@@ -876,13 +894,14 @@ qs_status qs_adjoint(qs_circuit* c, const double* params, const qs_obs* H, qs_st
     double E = 0.0;
     hipck(hipMemcpyAsync(&E, part + kGridMax, sizeof(double), hipMemcpyDeviceToHost, st), "energy");
     const int ns = c->hc.plan.ngrad_slots;
-    c->gpart.ensure(sizeof(double) * (size_t(std::max(ns, 1)) * kGridMax));
+    c->gpart.ensure(sizeof(double) * (size_t(std::max(ns, 1)) * kGradStride));
     c->gout.ensure(sizeof(double) * std::max(ns, 1));
-    if (ns > 0) hipck(launch_zero(c->gpart.as<double>(), int64_t(ns) * kGridMax, st), "zero");
+    if (ns > 0) hipck(launch_zero(c->gpart.as<double>(), int64_t(ns) * kGradStride, st), "zero");
     run_passes(c->dev, c->hc.plan, psi->dbl(), psi->ptr, lam->ptr, dpar, nullptr, c->gpart.as<double>(), st);
     std::vector<double> slots(ns);
     if (ns > 0) {
-      hipck(launch_slot_sums(c->gpart.as<double>(), ns, kGridMax, c->gout.as<double>(), st), "slot sums");
+      hipck(launch_slot_sums(c->gpart.as<double>(), ns, kGradStride, kGradStride, c->gout.as<double>(), st),
+            "slot sums");
       hipck(hipMemcpyAsync(slots.data(), c->gout.p, sizeof(double) * ns, hipMemcpyDeviceToHost, st), "grad");
     }
     hipck(hipStreamSynchronize(st), "sync");

@@ -16,18 +16,26 @@ struct DevPlan {
   const PhaseRec* phases = nullptr;
   const void* qtab = nullptr;     // complex table in the state precision
   const double* qang = nullptr;   // the same table as angles
+  const StageRec* stages = nullptr;
+  const int32_t* phlist = nullptr;
+  const double* btab = nullptr;
+  void* matc = nullptr;           // matrix pool in the state precision (rotation slots written per run)
+  int nops_total = 0;
 };
 
 constexpr int kGridMax = 2048;  // fixed upper bound on streaming grids (deterministic reductions)
+constexpr int kGradStride = kGridMax * 4;  // adjoint partials: one slot per (block, wave)
 
 int tile_grid(const PassGeom& g);
 
 // One tiled pass.  psi2 != nullptr selects the two-state (adjoint) kernel:
 // ops run in reverse with inverse matrices on psi and psi2, and every
 // trainable rotation writes Im<psi2|Pc P psi> partials to
-// gpart[gslot * kGridMax + block] before being undone.
+// gpart[gslot * kGradStride + block * 4 + wave] before being undone.
 hipError_t launch_tile_pass(bool dbl, void* psi, void* psi2, const PassGeom& g, const DevPlan& dp,
                             const double* params, const double* scales, double* gpart, hipStream_t s);
+// Fill the forward and inverse matrices of every rotation op from params.
+hipError_t launch_rot_mats(bool dbl, const DevPlan& dp, const double* params, hipStream_t s);
 hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* tau, hipStream_t s);
 
 hipError_t launch_set_basis(bool dbl, void* psi, int n, uint64_t x, hipStream_t s);
@@ -50,8 +58,9 @@ hipError_t launch_apply_hamiltonian(bool dbl, const void* psi, void* lam, int n,
                                     const int* group_off, int ngroups, const PauliTermDev* terms,
                                     hipStream_t s);
 hipError_t launch_final_sum(const double* partials, int count, double* out, hipStream_t s);
-// out[slot] = sum of partials[slot*kGridMax + b], b < nblocks, for every slot
-hipError_t launch_slot_sums(const double* partials, int nslots, int nblocks, double* out, hipStream_t s);
+// out[slot] = sum of partials[slot*stride + b], b < nblocks, for every slot
+hipError_t launch_slot_sums(const double* partials, int nslots, int nblocks, int stride, double* out,
+                            hipStream_t s);
 
 // Sampling (see qsim.h): block sums, scan, per-shot search.
 hipError_t launch_sample(bool dbl, const void* psi, int n, double* blocksums, double* prefix, int64_t shots,

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_tile(typename CT<R>::C* __restrict__ ps
           const double th = (TWO ? -1.0 : 1.0) * params[op.pidx];
           if (TWO && op.gslot >= 0) {
             const double v = block_sum(rot_grad_partial(t1, t2, M, op.b[0], op.cin, op.pauli), red);
-            if (tid == 0) gpart[(int64_t)op.gslot * kGridMax + blockIdx.x] += v;
+            if (tid == 0) gpart[(int64_t)op.gslot * kGradStride + blockIdx.x * 4] += v;
           }
           double s, c;
           sincos(0.5 * th, &s, &c);
@@ -365,11 +365,36 @@ __global__ __launch_bounds__(256) void k_tile(typename CT<R>::C* __restrict__ ps
 // ----------------------------------------------------------------------------
 // involutive bit permutation: the amplitude at x moves to tau(x)
 // ----------------------------------------------------------------------------
+// XOR the 16-byte granule index inside a 256-byte LDS row with higher index
+// bits, so that threads walking any run of tile bits spread over the banks.
+template <typename R> __device__ __forceinline__ uint32_t swz(uint32_t j);
+template <> __device__ __forceinline__ uint32_t swz<float>(uint32_t j) {
+  return j ^ (((j >> 4) ^ (j >> 8)) & 30u);
+}
+template <> __device__ __forceinline__ uint32_t swz<double>(uint32_t j) {
+  return j ^ (((j >> 4) ^ (j >> 8)) & 15u);
+}
+
 struct PermArgs {
   int tau[kMaxQubits];
 };
 
+// the 16-byte vector of amplitudes t[idx[e]], t[idx[e+1]], ...
 template <typename R>
+__device__ __forceinline__ typename CT<R>::V gather_vec(const typename CT<R>::C* t, const uint16_t* idx, int e);
+template <>
+__device__ __forceinline__ float4 gather_vec<float>(const float2* t, const uint16_t* idx, int e) {
+  const float2 a = t[swz<float>(idx[e])], b = t[swz<float>(idx[e + 1])];
+  return make_float4(a.x, a.y, b.x, b.y);
+}
+template <>
+__device__ __forceinline__ double2 gather_vec<double>(const double2* t, const uint16_t* idx, int e) {
+  return t[swz<double>(idx[e])];
+}
+
+// NLD > 0: exactly NLD 16-byte vectors per thread and tile; NLD == 0: tiles
+// smaller than one vector per thread (guarded)
+template <typename R, int NLD>
 __global__ __launch_bounds__(256) void k_perm(typename CT<R>::C* __restrict__ psi, const PassGeom g,
                                               const PermArgs pa, int64_t ntiles) {
   using C = typename CT<R>::C;
@@ -380,10 +405,16 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::C* __restrict__ ps
   uint16_t* ltau = reinterpret_cast<uint16_t*>(tb + M);
   __shared__ uint64_t hoff[128];
   __shared__ int loc[kMaxQubits];
+  __shared__ int tau[kMaxQubits];
+  __shared__ int hb[kMaxTileBits];
   const int tid = threadIdx.x, L = g.L, H = g.H;
-  for (int b = tid; b < g.n; b += blockDim.x) loc[b] = b < L ? b : -1;
+  for (int b = tid; b < g.n; b += blockDim.x) {
+    loc[b] = b < L ? b : -1;
+    tau[b] = pa.tau[b];
+  }
+  if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
   __syncthreads();
-  if (tid < H) loc[g.hbits[tid]] = L + tid;
+  if (tid < H) loc[hb[tid]] = L + tid;
   for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
     uint64_t off = 0;
     for (int i = 0; i < H; ++i)
@@ -395,30 +426,55 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::C* __restrict__ ps
     uint32_t lj = 0;
     for (int i = 0; i < g.m; ++i)
       if ((j >> i) & 1) {
-        const int gp = i < L ? i : g.hbits[i - L];
-        lj |= 1u << loc[pa.tau[gp]];
+        const int gp = i < L ? i : hb[i - L];
+        lj |= 1u << loc[tau[gp]];
       }
     ltau[j] = (uint16_t)lj;
   }
   __syncthreads();
   const uint32_t lomask = (1u << L) - 1u;
+  using VT = typename CT<R>::V;
+  constexpr int VW = CT<R>::VW;
+  constexpr int kMaxLd = NLD > 0 ? NLD : 1;
+  auto off = [&](int e) { return hoff[e >> L] | (uint64_t)(e & lomask); };
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint64_t base = tile_base((uint64_t)t, g);
+    uint64_t base = (uint64_t)t << L;
+    for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
     uint64_t pbase = 0;
-    for (uint64_t r = base; r; r &= r - 1) pbase |= 1ull << pa.tau[__builtin_ctzll(r)];
-    const int64_t tp = (int64_t)tile_index(pbase, g);
+    for (uint64_t r = base; r; r &= r - 1) pbase |= 1ull << tau[__builtin_ctzll(r)];
+    uint64_t tpu = pbase >> L;  // the partner's tile index: its bits outside the tile, packed
+    for (int i = H - 1; i >= 0; --i) {
+      const int p = hb[i] - L;
+      tpu = (tpu & ((1ull << p) - 1ull)) | ((tpu >> (p + 1)) << p);
+    }
+    const int64_t tp = (int64_t)tpu;
     if (tp < t) continue;  // the partner tile's workgroup moves this pair
     const bool self = tp == t;
-    for (int e = tid; e < M; e += blockDim.x) {
-      const uint64_t off = hoff[e >> L] | (uint64_t)(e & lomask);
-      ta[e] = psi[base | off];
-      if (!self) tb[e] = psi[pbase | off];
+    VT ba[kMaxLd], bb[kMaxLd];  // every load of both tiles is issued before the LDS writes
+#pragma unroll
+    for (int u = 0; u < kMaxLd; ++u) {
+      const int e = (u * (int)blockDim.x + tid) * VW;
+      if (NLD > 0 || e < M) {  // a self-paired tile is simply read twice
+        ba[u] = *reinterpret_cast<const VT*>(psi + (base | off(e)));
+        bb[u] = *reinterpret_cast<const VT*>(psi + (pbase | off(e)));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kMaxLd; ++u) {
+      const int e = (u * (int)blockDim.x + tid) * VW;
+      if (NLD > 0 || e < M) {
+        *reinterpret_cast<VT*>(ta + swz<R>(e)) = ba[u];
+        *reinterpret_cast<VT*>(tb + swz<R>(e)) = bb[u];
+      }
     }
     __syncthreads();
-    for (int e = tid; e < M; e += blockDim.x) {
-      const uint64_t off = hoff[e >> L] | (uint64_t)(e & lomask);
-      psi[pbase | off] = ta[ltau[e]];
-      if (!self) psi[base | off] = tb[ltau[e]];
+#pragma unroll
+    for (int u = 0; u < kMaxLd; ++u) {
+      const int e = (u * (int)blockDim.x + tid) * VW;
+      if (NLD > 0 || e < M) {
+        *reinterpret_cast<VT*>(psi + (pbase | off(e))) = gather_vec<R>(ta, ltau, e);
+        if (!self) *reinterpret_cast<VT*>(psi + (base | off(e))) = gather_vec<R>(tb, ltau, e);
+      }
     }
     __syncthreads();
   }
@@ -561,10 +617,11 @@ __global__ __launch_bounds__(256) void k_final_sum(const double* __restrict__ pa
   if (threadIdx.x == 0) out[0] = r;
 }
 
-__global__ __launch_bounds__(256) void k_slot_sums(const double* __restrict__ part, int nblocks, double* out) {
+__global__ __launch_bounds__(256) void k_slot_sums(const double* __restrict__ part, int nblocks, int stride,
+                                                  double* out) {
   __shared__ double red[8];
   double acc = 0.0;
-  const double* p = part + (int64_t)blockIdx.x * kGridMax;
+  const double* p = part + (int64_t)blockIdx.x * stride;
   for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += p[i];
   const double r = block_sum(acc, red);
   if (threadIdx.x == 0) out[blockIdx.x] = r;
@@ -713,8 +770,472 @@ __global__ __launch_bounds__(256) void k_samp_shots(const typename CT<R>::C* __r
   }
 }
 
+// ----------------------------------------------------------------------------
+// staged tiled pass: the tile sits in LDS (bank-swizzled); each stage gathers
+// 2^kRegBits amplitudes per thread, applies its ops in registers, scatters.
+// ----------------------------------------------------------------------------
+constexpr int NR = kRegBits;
+constexpr int NE = 1 << kRegBits;
+
+
+template <typename C> __device__ __forceinline__ C expi(double a);
+template <> __device__ __forceinline__ float2 expi<float2>(double a) {
+  const double r = a - 6.283185307179586 * rint(a * 0.15915494309189535);
+  float s, c;
+  sincosf((float)r, &s, &c);
+  return make_float2(c, s);
+}
+template <> __device__ __forceinline__ double2 expi<double2>(double a) {
+  double s, c;
+  sincos(a, &s, &c);
+  return make_double2(c, s);
+}
+
+template <int K, bool REAL, typename C>
+__device__ __forceinline__ void r1(C* v, C m00, C m01, C m10, C m11, uint32_t creg) {
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    if (e & (1 << K)) continue;
+    if ((e & creg) != creg) continue;
+    const int f = e | (1 << K);
+    const C a = v[e], b = v[f];
+    if (REAL) {
+      v[e].x = m00.x * a.x + m01.x * b.x;
+      v[e].y = m00.x * a.y + m01.x * b.y;
+      v[f].x = m10.x * a.x + m11.x * b.x;
+      v[f].y = m10.x * a.y + m11.x * b.y;
+    } else {
+      v[e] = cmadd(cmul(m00, a), m01, b);
+      v[f] = cmadd(cmul(m10, a), m11, b);
+    }
+  }
+}
+
+template <bool REAL, typename C>
+__device__ __forceinline__ void r1_any(C* v, int k, C m00, C m01, C m10, C m11, uint32_t creg) {
+  switch (k) {
+    case 0: r1<0, REAL>(v, m00, m01, m10, m11, creg); break;
+    case 1: r1<1, REAL>(v, m00, m01, m10, m11, creg); break;
+    case 2: r1<2, REAL>(v, m00, m01, m10, m11, creg); break;
+    default: r1<3, REAL>(v, m00, m01, m10, m11, creg); break;
+  }
+}
+
+template <int KH, int KL, typename C>
+__device__ __forceinline__ void r2(C* v, const C* __restrict__ mm, uint32_t creg) {
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    if (e & ((1 << KH) | (1 << KL))) continue;
+    if ((e & creg) != creg) continue;
+    const int i1 = e | (1 << KL), i2 = e | (1 << KH), i3 = i1 | i2;
+    const C a0 = v[e], a1 = v[i1], a2 = v[i2], a3 = v[i3];
+    C o[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      C acc = cmul(mm[4 * r], a0);
+      acc = cmadd(acc, mm[4 * r + 1], a1);
+      acc = cmadd(acc, mm[4 * r + 2], a2);
+      o[r] = cmadd(acc, mm[4 * r + 3], a3);
+    }
+    v[e] = o[0];
+    v[i1] = o[1];
+    v[i2] = o[2];
+    v[i3] = o[3];
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ void r2_any(C* v, int kh, int kl, const C* __restrict__ mp, uint32_t creg) {
+  switch (kh * 4 + kl) {
+    case 4: r2<1, 0>(v, mp, creg); break;
+    case 8: r2<2, 0>(v, mp, creg); break;
+    case 9: r2<2, 1>(v, mp, creg); break;
+    case 12: r2<3, 0>(v, mp, creg); break;
+    case 13: r2<3, 1>(v, mp, creg); break;
+    default: r2<3, 2>(v, mp, creg); break;
+  }
+}
+
+// k-qubit matrix on register slots 0..K-1 (slot K-1 = matrix MSB)
+template <int K, typename C>
+__device__ __forceinline__ void rk(C* v, const double* mp, uint32_t creg) {
+  constexpr int D = 1 << K;
+#pragma unroll
+  for (int g0 = 0; g0 < NE; g0 += D) {
+    if ((g0 & creg) != creg) continue;
+    C in[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) in[i] = v[g0 + i];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      C acc = mk<C>(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc = cmadd(acc, ldm<C>(mp, r * D + c), in[c]);
+      v[g0 + r] = acc;
+    }
+  }
+}
+
+template <int K, bool TWO, typename C>
+__device__ __forceinline__ void phase1(C* v, C* w, C F, bool wtriv, bool wscaled, const C* __restrict__ qt,
+                                       const double* __restrict__ qa, double scl) {
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    if (!(e & (1 << K))) continue;
+    C fe = F;
+    if (!wtriv) {
+      C wr;
+      if (wscaled) wr = expi<C>(scl * qa[e]);
+      else wr = TWO ? cconj(qt[e]) : qt[e];
+      fe = cmul(fe, wr);
+    }
+    v[e] = cmul(v[e], fe);
+    if (TWO) w[e] = cmul(w[e], fe);
+  }
+}
+
+template <int K, typename C>
+__device__ __forceinline__ double rgrad(const C* ps, const C* la, uint32_t creg, int pauli) {
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    if (e & (1 << K)) continue;
+    if ((e & creg) != creg) continue;
+    const int f = e | (1 << K);
+    const C p0 = ps[e], p1 = ps[f], l0 = la[e], l1 = la[f];
+    double q0r, q0i, q1r, q1i;
+    if (pauli == 1) { q0r = p1.x; q0i = p1.y; q1r = p0.x; q1i = p0.y; }
+    else if (pauli == 2) { q0r = p1.y; q0i = -p1.x; q1r = -p0.y; q1i = p0.x; }
+    else { q0r = p0.x; q0i = p0.y; q1r = -p1.x; q1i = -p1.y; }
+    acc += (double)l0.x * q0i - (double)l0.y * q0r + (double)l1.x * q1i - (double)l1.y * q1r;
+  }
+  return acc;
+}
+
+template <typename C>
+__device__ __forceinline__ double rgrad_any(const C* ps, const C* la, int k, uint32_t creg, int pauli) {
+  switch (k) {
+    case 0: return rgrad<0>(ps, la, creg, pauli);
+    case 1: return rgrad<1>(ps, la, creg, pauli);
+    case 2: return rgrad<2>(ps, la, creg, pauli);
+    default: return rgrad<3>(ps, la, creg, pauli);
+  }
+}
+
+template <typename R, bool TWO, int NLD>
+__global__ __launch_bounds__(256) void k_tile2(
+    typename CT<R>::C* __restrict__ psi, typename CT<R>::C* __restrict__ lam, const PassGeom g,
+    const TileOp* __restrict__ ops, const StageRec* __restrict__ stages,
+    const typename CT<R>::C* __restrict__ matc, const PhaseRec* __restrict__ phases,
+    const int32_t* __restrict__ phlist, const double* __restrict__ dpool, const double* __restrict__ btab,
+    const typename CT<R>::C* __restrict__ qtab, const double* __restrict__ qang,
+    const double* __restrict__ scales, double* __restrict__ gpart, int64_t ntiles) {
+  using C = typename CT<R>::C;
+  using VT = typename CT<R>::V;
+  constexpr int VW = CT<R>::VW;
+  extern __shared__ __align__(16) char smem[];
+  const int M = 1 << g.m;
+  C* t1 = reinterpret_cast<C*>(smem);
+  C* t2 = TWO ? t1 + M : nullptr;
+  __shared__ uint64_t hoff[128];
+  __shared__ double phA[kMaxPhasePerPass];
+  __shared__ double phNu[kMaxPhasePerPass][kMaxTileBits];
+  __shared__ double phA0[kMaxPhasePerPass];
+  __shared__ double phNu0[kMaxPhasePerPass][kMaxTileBits];
+  __shared__ double phCk[kMaxPhasePerPass][kMaxKBits];
+  __shared__ int hb[kMaxTileBits];
+  __shared__ int kpos[kMaxKBits];
+
+  const int tid = threadIdx.x;
+  const int L = g.L, H = g.H, m = g.m, n = g.n;
+  const int nph = g.nph, ph0 = g.ph0, nst = g.nst, st0 = g.st0, op0 = g.op0;
+  const int gbits = __builtin_ctz(gridDim.x);   // the grid is a power of two
+  const int kb = (n - m) - gbits;
+  if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
+  if (tid == 0) {  // global positions of the tile-index bits above the grid
+    int idx = 0;
+    uint64_t tm = (1ull << L) - 1;
+    for (int i = 0; i < H; ++i) tm |= 1ull << g.hbits[i];
+    for (int q = 0; q < n; ++q) {
+      if ((tm >> q) & 1) continue;
+      if (idx >= gbits && idx - gbits < kMaxKBits) kpos[idx - gbits] = q;
+      ++idx;
+    }
+  }
+  for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
+    uint64_t off = 0;
+    for (int i = 0; i < H; ++i)
+      if ((hc >> i) & 1) off |= 1ull << g.hbits[i];
+    hoff[hc] = off;
+  }
+  __syncthreads();
+  const uint32_t lomask = (1u << L) - 1u;
+  auto pos = [&](int b) { return b < L ? b : hb[b - L]; };
+  // every thread moves NLD 16-byte vectors per tile and state
+  auto tbase = [&](int64_t tt) {
+    uint64_t b = (uint64_t)tt << L;
+    for (int i = 0; i < H; ++i) b = insert_zero64(b, hb[i]);
+    return b;
+  };
+  auto gaddr = [&](uint64_t b, int u) {
+    const int e = (u * (int)blockDim.x + tid) * VW;
+    return b | hoff[e >> L] | (uint64_t)(e & lomask);
+  };
+  // phase polynomials, part fixed for this workgroup (tile t0 = blockIdx.x,
+  // k bits zero): constant, tile-bit coefficients and k-bit coefficients
+  {
+    const uint64_t base0 = tbase(blockIdx.x);
+    for (int idx = tid; idx < nph * 32; idx += blockDim.x) {
+      const int p = idx >> 5, r = idx & 31;
+      const PhaseRec rec = phases[phlist[ph0 + p]];
+      const double* P = dpool + rec.dpool;
+      const double scl = (rec.scale_idx >= 0 ? scales[rec.scale_idx] : 1.0) * (TWO ? -1.0 : 1.0);
+      int q0 = -1;
+      double s = 0.0;
+      if (r < m) q0 = pos(r);
+      else if (r >= 14 && r - 14 < kb) {
+        q0 = kpos[r - 14];
+        s = P[1 + q0];
+      }
+      if (q0 >= 0) {
+        for (uint64_t rr = base0; rr; rr &= rr - 1) s += P[1 + n + q0 * n + __builtin_ctzll(rr)];
+        if (r < m) phNu0[p][r] = s * scl;
+        else phCk[p][r - 14] = s * scl;
+      } else if (r == 13) {
+        s = P[0];
+        for (uint64_t rr = base0; rr; rr &= rr - 1) {
+          const int q = __builtin_ctzll(rr);
+          s += P[1 + q];
+          for (uint64_t r2 = rr & (rr - 1); r2; r2 &= r2 - 1) s += P[1 + n + q * n + __builtin_ctzll(r2)];
+        }
+        phA0[p] = s * scl;
+      }
+    }
+    __syncthreads();
+  }
+
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t base = tbase(t);
+    for (int half = 0; half < (TWO ? 2 : 1); ++half) {
+      const C* src = half ? lam : psi;
+      C* dst = half ? t2 : t1;
+      VT buf[NLD];  // issue every load of the tile before the first LDS write
+#pragma unroll
+      for (int u = 0; u < NLD; ++u) buf[u] = *reinterpret_cast<const VT*>(src + gaddr(base, u));
+#pragma unroll
+      for (int u = 0; u < NLD; ++u) *reinterpret_cast<VT*>(dst + swz<R>((u * (int)blockDim.x + tid) * VW)) = buf[u];
+    }
+    // per-tile coefficients of the pass's phase polynomials (the part of theta
+    // fixed by the bits outside the tile) from the workgroup part and the k bits
+    {
+      const uint32_t kk = (uint32_t)((uint64_t)t >> gbits);
+      for (int idx = tid; idx < nph * 16; idx += blockDim.x) {
+        const int p = idx >> 4, b = idx & 15;
+        const PhaseRec rec = phases[phlist[ph0 + p]];
+        const double scl = (rec.scale_idx >= 0 ? scales[rec.scale_idx] : 1.0) * (TWO ? -1.0 : 1.0);
+        const double* kt = btab + rec.kt_off;
+        if (b < m) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < kMaxKBits; ++j)
+            if ((kk >> j) & 1) s += kt[b * kMaxKBits + j];
+          phNu[p][b] = phNu0[p][b] + scl * s;
+        } else if (b == 15) {
+          double s = phA0[p];
+#pragma unroll
+          for (int j = 0; j < kMaxKBits; ++j)
+            if ((kk >> j) & 1) s += phCk[p][j];
+          phA[p] = s + scl * kt[m * kMaxKBits + kk];
+        }
+      }
+      __syncthreads();
+    }
+
+    for (int si = 0; si < nst; ++si) {
+      const StageRec st = stages[st0 + (TWO ? nst - 1 - si : si)];
+      const uint32_t rm0 = 1u << st.rb[0], rm1 = 1u << st.rb[1], rm2 = 1u << st.rb[2], rm3 = 1u << st.rb[3];
+      // tile index of register element e: jg | (bits of e placed at the stage's register bits)
+      auto jr = [&](int e) {
+        return ((e & 1) ? rm0 : 0u) | ((e & 2) ? rm1 : 0u) | ((e & 4) ? rm2 : 0u) | ((e & 8) ? rm3 : 0u);
+      };
+      for (int gb = 0; gb < (M >> NR); gb += blockDim.x) {
+        const uint32_t jg = insert_zeros((uint32_t)(gb + tid), st.rbmask);
+        C v[NE], w[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          v[e] = t1[swz<R>(jg | jr(e))];
+          if (TWO) w[e] = t2[swz<R>(jg | jr(e))];
+        }
+        for (int oi = 0; oi < st.nops; ++oi) {
+          const int o = op0 + st.op0 + (TWO ? st.nops - 1 - oi : oi);
+          const int kind = ops[o].kind;
+          const bool act = ((base & ops[o].cout) == ops[o].cout) && ((jg & ops[o].cin) == ops[o].cin);
+          const uint32_t creg = ops[o].creg;
+          if (kind == OP_DENSE1 || kind == OP_ROT) {
+            const int k = ops[o].b[0];
+            if (TWO && kind == OP_ROT && ops[o].gslot >= 0) {
+              double pg = act ? rgrad_any(v, w, k, creg, ops[o].pauli) : 0.0;
+              for (int off = 32; off > 0; off >>= 1) pg += __shfl_xor(pg, off, 64);
+              if ((tid & 63) == 0)
+                gpart[(int64_t)ops[o].gslot * kGradStride + blockIdx.x * 4 + (tid >> 6)] += pg;
+            }
+            if (!act) continue;
+            const C* mp = matc + ops[o].mat + (TWO ? 4 : 0);
+            const C a = mp[0], b = mp[1], c = mp[2], d = mp[3];
+            if (ops[o].flags & 1u) {
+              r1_any<true>(v, k, a, b, c, d, creg);
+              if (TWO) r1_any<true>(w, k, a, b, c, d, creg);
+            } else {
+              r1_any<false>(v, k, a, b, c, d, creg);
+              if (TWO) r1_any<false>(w, k, a, b, c, d, creg);
+            }
+          } else if (kind == OP_DENSE2) {
+            if (!act) continue;
+            const C* mp = matc + ops[o].mat + (TWO ? 16 : 0);
+            r2_any(v, ops[o].b[0], ops[o].b[1], mp, creg);
+            if (TWO) r2_any(w, ops[o].b[0], ops[o].b[1], mp, creg);
+          } else if (kind == OP_PHASE && (ops[o].flags & 2u)) {
+            // every term holds register slot kb: the factor is 1 where that bit
+            // is 0, and exp(i beta_kb) * wr[e] where it is 1
+            if (!act) continue;
+            const int p = ops[o].pidx, kbs = ops[o].b[0];
+            const PhaseRec rec = phases[ops[o].aux];
+            const double scl = (rec.scale_idx >= 0 ? scales[rec.scale_idx] : 1.0) * (TWO ? -1.0 : 1.0);
+            const double* bt = btab + rec.bt_off + (gb + tid) * (NR + 1);
+            const int rbk = kbs == 0 ? st.rb[0] : kbs == 1 ? st.rb[1] : kbs == 2 ? st.rb[2] : st.rb[3];
+            const C F = expi<C>(phNu[p][rbk] + scl * bt[1 + kbs]);
+            const C* qt = qtab + rec.wr_off;
+            const bool wtriv = rec.wr_trivial != 0, wscaled = rec.scale_idx >= 0;
+            const double* qa = qang + rec.wr_off;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+              if (!((e >> kbs) & 1)) continue;
+              C fe = F;
+              if (!wtriv) {
+                C wr;
+                if (wscaled) wr = expi<C>(scl * qa[e]);
+                else wr = TWO ? cconj(qt[e]) : qt[e];
+                fe = cmul(fe, wr);
+              }
+              v[e] = cmul(v[e], fe);
+              if (TWO) w[e] = cmul(w[e], fe);
+            }
+          } else if (kind == OP_PHASE) {
+            if (!act) continue;
+            const int p = ops[o].pidx;
+            const PhaseRec rec = phases[ops[o].aux];
+            const double scl = (rec.scale_idx >= 0 ? scales[rec.scale_idx] : 1.0) * (TWO ? -1.0 : 1.0);
+            const double* bt = btab + rec.bt_off + (gb + tid) * (NR + 1);
+            double th = phA[p] + scl * bt[0];
+            for (uint32_t r = jg; r; r &= r - 1) th += phNu[p][__builtin_ctz(r)];
+            // factor of register element e: exp(i th) * prod_{k in e} F_k * wr[e],
+            // walked in Gray-code order with one running product
+            const C F0 = expi<C>(phNu[p][st.rb[0]] + scl * bt[1]);
+            const C F1 = expi<C>(phNu[p][st.rb[1]] + scl * bt[2]);
+            const C F2 = expi<C>(phNu[p][st.rb[2]] + scl * bt[3]);
+            const C F3 = expi<C>(phNu[p][st.rb[3]] + scl * bt[4]);
+            const C* qt = qtab + rec.wr_off;
+            // factor of register element e = exp(i th) * prod_{k in e} F_k (* wr[e]):
+            // a product tree over the four register bits, written out
+            const C f0 = expi<C>(th), f1 = cmul(f0, F0);
+            const C f2 = cmul(f0, F1), f3 = cmul(f1, F1);
+            const C f4 = cmul(f0, F2), f5 = cmul(f1, F2), f6 = cmul(f2, F2), f7 = cmul(f3, F2);
+            const C f8 = cmul(f0, F3), f9 = cmul(f1, F3), f10 = cmul(f2, F3), f11 = cmul(f3, F3);
+            const C f12 = cmul(f4, F3), f13 = cmul(f5, F3), f14 = cmul(f6, F3), f15 = cmul(f7, F3);
+            const bool wtriv = rec.wr_trivial != 0;
+            const bool wscaled = rec.scale_idx >= 0;
+            auto apply = [&](int e, C fe) {
+              if (!wtriv) {
+                C wr;
+                if (wscaled) wr = expi<C>(scl * qang[rec.wr_off + e]);
+                else wr = TWO ? cconj(qt[e]) : qt[e];
+                fe = cmul(fe, wr);
+              }
+              v[e] = cmul(v[e], fe);
+              if (TWO) w[e] = cmul(w[e], fe);
+            };
+            apply(0, f0); apply(1, f1); apply(2, f2); apply(3, f3);
+            apply(4, f4); apply(5, f5); apply(6, f6); apply(7, f7);
+            apply(8, f8); apply(9, f9); apply(10, f10); apply(11, f11);
+            apply(12, f12); apply(13, f13); apply(14, f14); apply(15, f15);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          t1[swz<R>(jg | jr(e))] = v[e];
+          if (TWO) t2[swz<R>(jg | jr(e))] = w[e];
+        }
+      }
+      __syncthreads();
+    }
+
+    for (int half = 0; half < (TWO ? 2 : 1); ++half) {
+      C* dstg = half ? lam : psi;
+      const C* src = half ? t2 : t1;
+      VT buf[NLD];
+#pragma unroll
+      for (int u = 0; u < NLD; ++u) buf[u] = *reinterpret_cast<const VT*>(src + swz<R>((u * (int)blockDim.x + tid) * VW));
+#pragma unroll
+      for (int u = 0; u < NLD; ++u) *reinterpret_cast<VT*>(dstg + gaddr(base, u)) = buf[u];
+    }
+    __syncthreads();
+  }
+}
+
+// forward and inverse rotation matrices, exp(-i theta P / 2) and its inverse
+template <typename R>
+__global__ void k_rot_mats(const TileOp* __restrict__ ops, int nops, const double* __restrict__ params,
+                           typename CT<R>::C* __restrict__ matc) {
+  using C = typename CT<R>::C;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nops) return;
+  const TileOp op = ops[i];
+  if (op.kind != OP_ROT || op.mat < 0) return;
+  double s, c;
+  sincos(0.5 * params[op.pidx], &s, &c);
+  C* m = matc + op.mat;
+  for (int inv = 0; inv < 2; ++inv) {
+    const double si = inv ? -s : s;
+    C* o = m + 4 * inv;
+    if (op.pauli == 1) {
+      o[0] = mk<C>(c, 0); o[1] = mk<C>(0, -si); o[2] = mk<C>(0, -si); o[3] = mk<C>(c, 0);
+    } else if (op.pauli == 2) {
+      o[0] = mk<C>(c, 0); o[1] = mk<C>(-si, 0); o[2] = mk<C>(si, 0); o[3] = mk<C>(c, 0);
+    } else {
+      o[0] = mk<C>(c, -si); o[1] = mk<C>(0, 0); o[2] = mk<C>(0, 0); o[3] = mk<C>(c, si);
+    }
+  }
+}
+
+hipError_t set_lds_fn(void* fn, size_t lds) {
+  if (lds <= 32768) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <typename R> void* fn_tile(bool two) {
   return two ? (void*)k_tile<R, true> : (void*)k_tile<R, false>;
+}
+template <typename R, int NLD> void* fn_tile2(bool two) {
+  return two ? (void*)k_tile2<R, true, NLD> : (void*)k_tile2<R, false, NLD>;
+}
+
+template <typename R, int NLD>
+hipError_t launch_tile2_t(void* psi, void* psi2, const PassGeom& g, const DevPlan& dp, const double* params,
+                          const double* scales, double* gpart, int64_t nt, int grid, size_t lds, hipStream_t s) {
+  using C = typename CT<R>::C;
+  const bool two = psi2 != nullptr;
+  hipError_t e = set_lds_fn(fn_tile2<R, NLD>(two), lds);
+  if (e != hipSuccess) return e;
+  (void)params;
+  if (two)
+    hipLaunchKernelGGL((k_tile2<R, true, NLD>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, (C*)psi2, g, dp.ops,
+                       dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab, (const C*)dp.qtab,
+                       dp.qang, scales, gpart, nt);
+  else
+    hipLaunchKernelGGL((k_tile2<R, false, NLD>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, nullptr, g, dp.ops,
+                       dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab, (const C*)dp.qtab,
+                       dp.qang, scales, gpart, nt);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -753,6 +1274,14 @@ hipError_t launch_tile_pass(bool dbl, void* psi, void* psi2, const PassGeom& g, 
   const size_t esz = dbl ? 16 : 8;
   const bool two = psi2 != nullptr;
   const size_t lds = (size_t(1) << g.m) * esz * (two ? 2 : 1);
+  if (g.kern == 2) {
+    if (g.m < 12 || g.nst < 1 || g.nph < 0 || g.nph > kMaxPhasePerPass) return hipErrorInvalidValue;
+    const int nld = (1 << g.m) / (kThreads * (dbl ? 1 : 2));
+    if (dbl && nld == 16) return launch_tile2_t<double, 16>(psi, psi2, g, dp, params, scales, gpart, nt, grid, lds, s);
+    if (!dbl && nld == 8) return launch_tile2_t<float, 8>(psi, psi2, g, dp, params, scales, gpart, nt, grid, lds, s);
+    if (!dbl && nld == 16) return launch_tile2_t<float, 16>(psi, psi2, g, dp, params, scales, gpart, nt, grid, lds, s);
+    return hipErrorInvalidValue;
+  }
   void* fn = dbl ? fn_tile<double>(two) : fn_tile<float>(two);
   {
     hipError_t e = set_lds(fn, lds);
@@ -776,6 +1305,40 @@ hipError_t launch_tile_pass(bool dbl, void* psi, void* psi2, const PassGeom& g, 
   return hipGetLastError();
 }
 
+hipError_t launch_rot_mats(bool dbl, const DevPlan& dp, const double* params, hipStream_t s) {
+  if (dp.nops_total <= 0 || !params) return hipSuccess;
+  const int grid = (dp.nops_total + 255) / 256;
+  if (dbl)
+    hipLaunchKernelGGL((k_rot_mats<double>), dim3(grid), dim3(256), 0, s, dp.ops, dp.nops_total, params,
+                       (double2*)dp.matc);
+  else
+    hipLaunchKernelGGL((k_rot_mats<float>), dim3(grid), dim3(256), 0, s, dp.ops, dp.nops_total, params,
+                       (float2*)dp.matc);
+  return hipGetLastError();
+}
+
+template <typename R, int NLD>
+hipError_t perm_launch_t(void* psi, const PassGeom& g, const PermArgs& pa, int64_t nt, int grid, size_t lds,
+                         hipStream_t s) {
+  hipError_t e = set_lds_fn((void*)k_perm<R, NLD>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_perm<R, NLD>), dim3(grid), dim3(kThreads), lds, s, (typename CT<R>::C*)psi, g, pa, nt);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t perm_launch(int nld, void* psi, const PassGeom& g, const PermArgs& pa, int64_t nt, int grid, size_t lds,
+                       hipStream_t s) {
+  switch (nld) {
+    case 0: return perm_launch_t<R, 0>(psi, g, pa, nt, grid, lds, s);
+    case 1: return perm_launch_t<R, 1>(psi, g, pa, nt, grid, lds, s);
+    case 2: return perm_launch_t<R, 2>(psi, g, pa, nt, grid, lds, s);
+    case 4: return perm_launch_t<R, 4>(psi, g, pa, nt, grid, lds, s);
+    case 8: return perm_launch_t<R, 8>(psi, g, pa, nt, grid, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* tau, hipStream_t s) {
   PermArgs pa;
   for (int i = 0; i < kMaxQubits; ++i) pa.tau[i] = i < g.n ? tau[i] : i;
@@ -792,15 +1355,10 @@ hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* t
   const int grid = (int)(nt < kGridMax ? nt : kGridMax);
   const size_t esz = dbl ? 16 : 8;
   const size_t lds = (size_t(1) << g.m) * (2 * esz + 2);
-  {
-    hipError_t e = set_lds(dbl ? (void*)k_perm<double> : (void*)k_perm<float>, lds);
-    if (e != hipSuccess) return e;
-  }
-  if (dbl)
-    hipLaunchKernelGGL((k_perm<double>), dim3(grid), dim3(kThreads), lds, s, (double2*)psi, g, pa, nt);
-  else
-    hipLaunchKernelGGL((k_perm<float>), dim3(grid), dim3(kThreads), lds, s, (float2*)psi, g, pa, nt);
-  return hipGetLastError();
+  const int nld = (1 << g.m) / (kThreads * (dbl ? 1 : 2));
+  if (nld > 8) return hipErrorInvalidValue;
+  return dbl ? perm_launch<double>(nld, psi, g, pa, nt, grid, lds, s)
+             : perm_launch<float>(nld, psi, g, pa, nt, grid, lds, s);
 }
 
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s) {
@@ -887,9 +1445,10 @@ hipError_t launch_final_sum(const double* partials, int count, double* out, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_slot_sums(const double* partials, int nslots, int nblocks, double* out, hipStream_t s) {
+hipError_t launch_slot_sums(const double* partials, int nslots, int nblocks, int stride, double* out,
+                            hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_slot_sums, dim3(nslots), dim3(256), 0, s, partials, nblocks, out);
+  hipLaunchKernelGGL(k_slot_sums, dim3(nslots), dim3(256), 0, s, partials, nblocks, stride, out);
   return hipGetLastError();
 }
 

@@ -84,6 +84,7 @@ struct RawOp {
   int kind;  // OP_*
   BitGate g;
   PhasePoly poly;  // OP_PHASE
+  int scale_idx = -1;
 };
 
 }  // namespace
@@ -127,7 +128,7 @@ int named_gate(const std::string& name, double theta, std::vector<cd>& out) {
 }
 
 void default_tile(int n, bool dbl, const TuneOpts& o, int* m, int* L) {
-  int mm = o.tile_bits > 0 ? o.tile_bits : (dbl ? 11 : 12);
+  int mm = o.tile_bits > 0 ? o.tile_bits : 12;
   int ll = o.low_bits > 0 ? o.low_bits : (dbl ? 5 : 6);
   mm = std::min(mm, dbl ? 12 : 13);  // <= 64 KiB of LDS per workgroup
   mm = std::max(mm, 6);
@@ -261,7 +262,10 @@ TileOp make_phase_op(Plan& plan, const PassGeom& g, const PhasePoly& P, int scal
   plan.dpool.insert(plan.dpool.end(), P.lam.begin(), P.lam.end());
   rec.qtab_off = (int)plan.qtab.size();
   rec.scale_idx = scale_idx;
-  rec.pad = 0;
+  rec.wr_off = -1;
+  rec.bt_off = -1;
+  rec.wr_trivial = 0;
+  rec.kt_off = -1;
   const int M = 1 << g.m;
   std::vector<double> ang(M, 0.0);
   for (int j = 1; j < M; ++j) {  // ang[j] = ang[j without its top bit] + the top bit's terms
@@ -309,6 +313,215 @@ PhasePoly ising_poly(int n, const double* J, const double* h) {
 
 namespace {
 
+int nphase_raw(const std::vector<RawOp>& raw) {
+  int c = 0;
+  for (const RawOp& r : raw) c += r.kind == OP_PHASE;
+  return c;
+}
+
+bool has(const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); }
+
+// Register-blocked form of a pass (tiles of >= 2^12 amplitudes): split its op
+// list into stages whose dense targets all lie in kRegBits tile bits, and
+// rewrite the ops in register-slot terms.
+void stage_pass(Plan& plan, Pass& ps) {
+  PassGeom& g = ps.geom;
+  g.kern = 1;
+  g.st0 = g.nst = g.ph0 = g.nph = 0;
+  if (g.m < 12) return;
+  int nph = 0;
+  for (const TileOp& op : ps.ops) {
+    if (op.kind == OP_DENSEK) return;  // k >= 3 matrices keep the one-sweep-per-op kernel
+    if (op.kind == OP_PHASE) ++nph;
+  }
+  if (nph > kMaxPhasePerPass) return;
+  const int n = g.n;
+  auto pos = [&](int local) { return local < g.L ? local : g.hbits[local - g.L]; };
+  auto targets = [](const TileOp& op) {
+    std::vector<int> s;
+    const int k = (op.kind == OP_DENSE1 || op.kind == OP_ROT) ? 1
+                  : op.kind == OP_DENSE2                     ? 2
+                  : op.kind == OP_DENSEK                     ? op.k
+                                                             : 0;
+    for (int t = 0; t < k; ++t) s.push_back(op.b[t]);
+    return s;
+  };
+  struct St {
+    std::vector<int> rb;
+    std::vector<TileOp> ops;
+  };
+  std::vector<St> sts;
+  St cur;
+  for (const TileOp& op : ps.ops) {
+    const std::vector<int> S = targets(op);
+    if (op.kind == OP_DENSEK) {  // slots 0..k-1 = targets, last target in slot 0
+      if (!cur.ops.empty()) sts.push_back(cur);
+      cur = St();
+      for (int t = op.k - 1; t >= 0; --t) cur.rb.push_back(op.b[t]);
+      cur.ops.push_back(op);
+      continue;
+    }
+    bool in = true;
+    for (int b : S) in &= has(cur.rb, b);
+    if (in) {
+      cur.ops.push_back(op);
+      continue;
+    }
+    std::vector<int> u = cur.rb;
+    for (int b : S)
+      if (!has(u, b)) u.push_back(b);
+    if ((int)u.size() <= kRegBits) {
+      cur.rb = u;
+      cur.ops.push_back(op);
+      continue;
+    }
+    sts.push_back(cur);
+    cur = St();
+    cur.rb = S;
+    cur.ops.push_back(op);
+  }
+  if (!cur.ops.empty()) sts.push_back(cur);
+
+  std::vector<TileOp> out;
+  g.st0 = (int)plan.stages.size();
+  g.ph0 = (int)plan.phlist.size();
+  g.nph = 0;
+  for (St& s : sts) {
+    for (int b = 0; (int)s.rb.size() < kRegBits; ++b)
+      if (!has(s.rb, b)) s.rb.push_back(b);
+    StageRec sr;
+    std::memset(&sr, 0, sizeof(sr));
+    int slot_of[kMaxTileBits];
+    for (int b = 0; b < kMaxTileBits; ++b) slot_of[b] = -1;
+    for (int k = 0; k < kRegBits; ++k) {
+      sr.rb[k] = s.rb[k];
+      sr.rbmask |= 1u << s.rb[k];
+      slot_of[s.rb[k]] = k;
+    }
+    sr.op0 = (int)out.size();
+    sr.nops = (int)s.ops.size();
+    for (TileOp op : s.ops) {
+      const uint32_t cin = op.cin;
+      op.cin = 0;
+      op.creg = 0;
+      for (uint32_t c = cin; c; c &= c - 1) {
+        const int b = __builtin_ctz(c);
+        if (slot_of[b] >= 0) op.creg |= 1u << slot_of[b];
+        else op.cin |= 1u << b;
+      }
+      const int dim = op.kind == OP_DENSE1 ? 2 : op.kind == OP_DENSE2 ? 4 : op.kind == OP_DENSEK ? (1 << op.k) : 0;
+      if (op.kind == OP_DENSE1 || op.kind == OP_ROT) {
+        op.b[0] = slot_of[op.b[0]];
+      } else if (op.kind == OP_DENSE2) {
+        int s0 = slot_of[op.b[0]], s1 = slot_of[op.b[1]];
+        if (s0 < s1) {  // make the higher slot the matrix MSB: swap the two index bits
+          static const int pm[4] = {0, 2, 1, 3};
+          for (int w = 0; w < 2; ++w) {
+            cd* M = plan.matpool.data() + op.mat + w * 16;
+            cd T[16];
+            for (int r = 0; r < 4; ++r)
+              for (int c = 0; c < 4; ++c) T[r * 4 + c] = M[pm[r] * 4 + pm[c]];
+            std::copy(T, T + 16, M);
+          }
+          std::swap(s0, s1);
+        }
+        op.b[0] = s0;
+        op.b[1] = s1;
+      } else if (op.kind == OP_DENSEK) {
+        for (int t = 0; t < op.k; ++t) op.b[t] = slot_of[op.b[t]];
+      } else if (op.kind == OP_PHASE) {
+        PhaseRec& rec = plan.phases[op.aux];
+        op.pidx = g.nph++;
+        plan.phlist.push_back(op.aux);
+        rec.wr_off = (int)plan.qtab.size();
+        const double* mu = plan.dpool.data() + rec.dpool + 1;
+        const double* lam = mu + n;
+        bool trivial = true;
+        for (int e = 0; e < (1 << kRegBits); ++e) {
+          double q = 0.0;
+          for (int k = 0; k < kRegBits; ++k)
+            for (int k2 = k + 1; k2 < kRegBits; ++k2)
+              if (((e >> k) & 1) && ((e >> k2) & 1)) q += lam[size_t(pos(s.rb[k])) * n + pos(s.rb[k2])];
+          trivial &= q == 0.0;
+          plan.qtab.push_back(std::polar(1.0, rec.scale_idx < 0 ? wrap_angle(q) : q));
+          plan.qang.push_back(rec.scale_idx < 0 ? wrap_angle(q) : q);
+        }
+        rec.wr_trivial = trivial ? 1 : 0;
+        // does every term of theta contain one register bit (a phase that is
+        // 1 wherever that bit is 0)?
+        for (int k = 0; k < kRegBits && !(op.flags & 2u); ++k) {
+          const int qb = pos(s.rb[k]);
+          bool one = plan.dpool[rec.dpool] == 0.0;
+          for (int p2 = 0; p2 < n && one; ++p2) {
+            if (p2 != qb && mu[p2] != 0.0) one = false;
+            for (int q2 = 0; q2 < n && one; ++q2)
+              if (p2 != qb && q2 != qb && lam[size_t(p2) * n + q2] != 0.0) one = false;
+          }
+          if (one) {
+            op.flags |= 2u;
+            op.b[0] = k;
+          }
+        }
+        // per thread group jg (register bits zero): theta_T(jg) and, for each
+        // register slot k, mu_k + sum_{a in jg} lam_{a,k}
+        // a workgroup visits tiles t = t0 + kk * G (G = 2^gb workgroups); the
+        // tile-index bits above gb ("k bits") sit at global positions kp[j]
+        {
+          const int ntb = n - g.m;
+          const int gb = std::min(ntb, kGridBits);
+          const int kb = ntb - gb;
+          if (kb > kMaxKBits) throw std::runtime_error("planner: too many tile-index bits");
+          std::vector<int> kp;
+          int idx = 0;
+          for (int q = 0; q < n; ++q) {
+            bool tile = q < g.L;
+            for (int h = 0; h < g.H; ++h) tile |= g.hbits[h] == q;
+            if (tile) continue;
+            if (idx >= gb) kp.push_back(q);
+            ++idx;
+          }
+          rec.kt_off = (int)plan.btab.size();
+          for (int b = 0; b < g.m; ++b)
+            for (int j = 0; j < kMaxKBits; ++j) plan.btab.push_back(j < kb ? lam[size_t(pos(b)) * n + kp[j]] : 0.0);
+          for (int kk = 0; kk < (1 << kb); ++kk) {
+            double q = 0.0;
+            for (int j = 0; j < kb; ++j)
+              for (int j2 = j + 1; j2 < kb; ++j2)
+                if (((kk >> j) & 1) && ((kk >> j2) & 1)) q += lam[size_t(kp[j]) * n + kp[j2]];
+            plan.btab.push_back(q);
+          }
+        }
+        rec.bt_off = (int)plan.btab.size();
+        const int ngr = 1 << (g.m - kRegBits);
+        for (int grp = 0; grp < ngr; ++grp) {
+          uint32_t jg = (uint32_t)grp;
+          for (int k2 = 0; k2 < g.m; ++k2)  // insert zeros at the register bits, ascending
+            if ((sr.rbmask >> k2) & 1) jg = ((jg >> k2) << (k2 + 1)) | (jg & ((1u << k2) - 1u));
+          plan.btab.push_back(plan.qang[rec.qtab_off + jg]);
+          for (int k = 0; k < kRegBits; ++k) {
+            const int pk = pos(s.rb[k]);
+            double b = mu[pk];
+            for (uint32_t r = jg; r; r &= r - 1) b += lam[size_t(pos(__builtin_ctz(r))) * n + pk];
+            plan.btab.push_back(b);
+          }
+        }
+      }
+      if (op.kind != OP_PHASE) op.flags = 0;
+      if (op.kind == OP_ROT && op.pauli == 2) op.flags |= 1u;
+      if (dim) {
+        bool real = true;
+        for (int i = 0; i < dim * dim; ++i) real &= plan.matpool[op.mat + i].imag() == 0.0;
+        if (real) op.flags |= 1u;
+      }
+      out.push_back(op);
+    }
+    plan.stages.push_back(sr);
+  }
+  g.nst = (int)sts.size();
+  ps.ops = out;
+  g.kern = 2;
+}
+
 // Close an open pass: fix the tile bit set, convert ops to tile-local form,
 // build the phase tables.
 void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& hsel,
@@ -344,7 +557,7 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
     op.sign = 1;
     op.kind = r.kind;
     if (r.kind == OP_PHASE) {
-      op = make_phase_op(plan, g, r.poly, -1);
+      op = make_phase_op(plan, g, r.poly, r.scale_idx);
     } else {
       const BitGate& bg = r.g;
       op.k = bg.k;
@@ -361,6 +574,8 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
         op.pidx = bg.pidx;
         op.pauli = bg.pauli == 'X' ? 1 : bg.pauli == 'Y' ? 2 : 3;
         if (bg.pidx >= 0) op.gslot = plan.ngrad_slots++;
+        op.mat = (int)plan.matpool.size();  // forward and inverse 2x2, written per run
+        plan.matpool.insert(plan.matpool.end(), 8, cd(0, 0));
       } else {
         const int dim = 1 << bg.k;
         op.mat = (int)plan.matpool.size();
@@ -371,7 +586,10 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
     }
     ps.ops.push_back(op);
   }
-  if (!ps.ops.empty()) plan.passes.push_back(ps);
+  if (!ps.ops.empty()) {
+    stage_pass(plan, ps);
+    plan.passes.push_back(ps);
+  }
   raw.clear();
   hsel.clear();
 }
@@ -505,6 +723,10 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
           ++it;
           continue;
         }
+        if (b.nmask && nphase_raw(raw) >= kMaxPhasePerPass - 2) {  // keep the pass staged
+          ++it;
+          continue;
+        }
         for (int bit : need) hsel.insert(bit);
         if (b.nmask) {
           PhasePoly Q = extract_terms(P, n, b.nmask, false);
@@ -543,6 +765,13 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
         ro.poly = std::move(Q);
         raw.push_back(std::move(ro));
       }
+    }
+    if (scheduled == G && C.tail_phase) {
+      RawOp ro;
+      ro.kind = OP_PHASE;
+      ro.poly = *C.tail_phase;
+      ro.scale_idx = 0;
+      raw.push_back(std::move(ro));
     }
     if (placed == 0 && raw.empty()) throw std::runtime_error("planner: no gate fits a tile");
     close_pass(plan, C, m, L, hsel, raw);
@@ -602,12 +831,8 @@ Plan plan_rx_layer(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly)
     g.pidx = 0;
     hc.gates.push_back(g);
   }
-  Plan p = plan_circuit(hc, opts, dbl);
-  if (poly) {
-    Pass& last = p.passes.back();
-    last.ops.push_back(make_phase_op(p, last.geom, *poly, 0));
-  }
-  return p;
+  hc.tail_phase = poly;
+  return plan_circuit(hc, opts, dbl);
 }
 
 }  // namespace qs

@@ -55,6 +55,9 @@ struct Plan {
   std::vector<PhaseRec> phases;
   std::vector<cd> qtab;          // exp(i theta_T(j)) per phase op
   std::vector<double> qang;      // theta_T(j) per phase op (same offsets as qtab)
+  std::vector<StageRec> stages;  // staged passes
+  std::vector<int32_t> phlist;   // staged passes: phase record of each per-pass phase slot
+  std::vector<double> btab;      // staged passes: per-group phase constants (PhaseRec::bt_off)
   int nparams = 0;
   int ngates = 0;
   int ngrad_slots = 0;           // ops carrying a trainable parameter
@@ -66,6 +69,7 @@ struct HostCircuit {
   std::vector<Gate> gates;
   int nparams = 0;
   TuneOpts opts;
+  const PhasePoly* tail_phase = nullptr;  // appended with scale slot 0 (adiabatic steps)
   bool compiled = false;
   Plan plan;
 };

@@ -23,6 +23,9 @@ enum OpKind : int32_t {
   OP_MFMA = 7,    // 2^k x 2^k matrix (k = 4, 5) applied with matrix-core instructions
 };
 
+// In a staged pass (kern == 2) b[] holds register slots instead of tile bits,
+// cin holds the controls on tile bits outside the registers and creg those on
+// register slots; OP_PHASE keeps its per-pass phase slot in pidx.
 struct TileOp {
   int32_t kind;
   int32_t k;         // number of target bits
@@ -35,7 +38,24 @@ struct TileOp {
   int32_t sign;      // OP_ROT: +1 forward, -1 inverse
   int32_t aux;       // OP_PHASE: phase record index; OP_DIAG: offset into diag pool
   int32_t gslot;     // adjoint: gradient slot of this op (-1 if none)
-  int32_t pad[2];
+  uint32_t creg;     // staged passes: control mask over register slots
+  uint32_t flags;    // bit 0: the matrix is real; bit 1 (OP_PHASE): every term holds register slot b[0]
+};
+
+constexpr int kRegBits = 4;            // register slots per thread in a staged pass
+constexpr int kMaxPhasePerPass = 16;   // phase ops whose tile terms are prepared per tile
+constexpr int kGridBits = 11;          // streaming grids hold at most 2^kGridBits workgroups
+constexpr int kMaxKBits = 12;          // tile-index bits above the grid: n - m - kGridBits <= 12
+
+// A stage of a staged pass: every thread gathers the 2^kRegBits amplitudes that
+// differ only in the tile bits rb[0..kRegBits-1], applies the stage's ops in
+// registers and writes them back.
+struct StageRec {
+  int32_t rb[kRegBits];  // tile-local bit held by register slot k
+  int32_t op0;
+  int32_t nops;
+  uint32_t rbmask;
+  int32_t pad;
 };
 
 // A quadratic phase polynomial theta(x) = c + sum_p mu_p x_p + sum_{p<q} lam_pq x_p x_q
@@ -50,7 +70,10 @@ struct PhaseRec {
   int32_t dpool;     // offset of c in the double pool
   int32_t qtab_off;  // offset in the complex phase-table pool
   int32_t scale_idx; // -1: scale 1; else theta is multiplied by scales[scale_idx]
-  int32_t pad;
+  int32_t wr_off;    // staged passes: exp(i Q_R(e)) over the register slots, 2^kRegBits entries
+  int32_t bt_off;    // staged passes: per thread group (theta_T(jg), beta_0..beta_3) pass constants
+  int32_t wr_trivial;  // 1 when Q_R(e) is zero for every e
+  int32_t kt_off;    // staged passes: lam(tile bit b, k-bit j) [m][kMaxKBits], then Q_k(kk) [2^kb]
 };
 
 // Per-pass geometry.
@@ -62,6 +85,9 @@ struct PassGeom {
   int32_t hbits[kMaxTileBits];  // global positions of the high tile bits, ascending
   int32_t nops;
   int32_t op0;          // first op in the op array
+  int32_t kern;         // 1: one LDS sweep per op; 2: register-blocked stages
+  int32_t st0, nst;     // staged passes: stage range
+  int32_t ph0, nph;     // staged passes: phase records prepared per tile
 };
 
 }  // namespace qs
