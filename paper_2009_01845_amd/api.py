@@ -382,3 +382,47 @@ class Circuit:
             except Exception:
                 pass
             self.h = None
+
+
+# ---------------------------------------------------------------------- batch
+def batch_create(circs, observables, dt="c64"):
+    arr_c = (C.c_void_p * len(circs))(*[c.h.value for c in circs])
+    arr_o = (C.c_void_p * len(observables))(*[o.h.value for o in observables])
+    h = C.c_void_p()
+    check(lib().qs_batch_create(len(circs), C.cast(arr_c, C.POINTER(C.c_void_p)),
+                                C.cast(arr_o, C.POINTER(C.c_void_p)), dtype_code(dt), None, C.byref(h)))
+    return h
+
+
+def batch_run(h, params_packed, count: int, nparams: int, want_grads: bool = True):
+    keep, pp = _f64(params_packed if nparams else np.zeros(1))
+    e = np.zeros(count)
+    g = np.zeros(max(1, nparams))
+    check(lib().qs_batch_run(h, pp, e.ctypes.data_as(_F64P), g.ctypes.data_as(_F64P) if want_grads else None))
+    return e, g[:nparams]
+
+
+def batch_destroy(h):
+    check(lib().qs_batch_destroy(h))
+
+
+class Batch:
+    """Many circuits with their own parameters and diagonal observables in
+    one persistent launch (captured as a HIP graph on the first run)."""
+
+    def __init__(self, circuits, observables, dtype="c64"):
+        self.circuits, self.observables = list(circuits), list(observables)  # keep the handles alive
+        self.nparams = sum(c.nparams for c in self.circuits)
+        self.h = batch_create(self.circuits, self.observables, dtype)
+
+    def run(self, params_packed, want_grads: bool = True):
+        return batch_run(self.h, params_packed, len(self.circuits), self.nparams, want_grads)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                batch_destroy(h)
+            except Exception:
+                pass
+            self.h = None

@@ -34,6 +34,46 @@ int tile_grid(const PassGeom& g);
 // gpart[gslot * kGradStride + block * 4 + wave] before being undone.
 hipError_t launch_tile_pass(bool dbl, void* psi, void* psi2, const PassGeom& g, const DevPlan& dp,
                             const double* params, const double* scales, double* gpart, hipStream_t s);
+struct PauliTermDev {
+  uint64_t zy;     // index bits carrying Z or Y
+  int32_t ny4;     // number of Y factors mod 4
+  int32_t pad;
+  double coeff;
+};
+
+// One instance of a batch: its plan lives at the given bases of the
+// concatenated pools (all offsets inside the records are instance-local).
+struct BatchInst {
+  int32_t n, npass, pass0, nops;
+  int32_t ops_base, st_base, mat_base, ph_base;
+  int32_t phl_base, dp_base, bt_base, qt_base;
+  int32_t param_base, nparams, slot_base, nslots;
+  int32_t obs_off, obs_nterms, pad0, pad1;
+  int64_t state_off, lam_off;  // elements of the batch state buffer
+};
+
+struct BatchArgs {
+  const BatchInst* insts = nullptr;
+  int count = 0;
+  const int32_t* order = nullptr;  // instances, largest first
+  int32_t* counter = nullptr;      // work queue head (zeroed before the launch)
+  const PassGeom* geoms = nullptr;
+  DevPlan dp;                      // concatenated pools; matc is written (rotations)
+  void* states = nullptr;
+  const double* params = nullptr;
+  const PauliTermDev* terms = nullptr;  // diagonal observables, per instance
+  const int32_t* slot_pidx = nullptr;
+  double* gpart = nullptr;         // 4 partials per gradient slot
+  double* energies = nullptr;
+  double* grads = nullptr;
+  int grid = 0;
+};
+
+// Persistent launch: workgroups take instances from the queue until it is
+// empty; each runs its instance's forward passes from |0..0>, the energy of
+// its diagonal observable, lambda = H psi, and the reverse adjoint sweep.
+hipError_t launch_batch(bool dbl, const BatchArgs& a, hipStream_t s);
+
 // Fill the forward and inverse matrices of every rotation op from params.
 hipError_t launch_rot_mats(bool dbl, const DevPlan& dp, const double* params, hipStream_t s);
 hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* tau, hipStream_t s);
@@ -45,12 +85,6 @@ hipError_t launch_set_plus(bool dbl, void* psi, int n, hipStream_t s);
 // `count` partials in a fixed order into out[0] (device).
 hipError_t launch_sumsq(bool dbl, const void* psi, int n, double* partials, hipStream_t s);
 hipError_t launch_dot_re(bool dbl, const void* a, const void* b, int n, double* partials, hipStream_t s);
-struct PauliTermDev {
-  uint64_t zy;     // index bits carrying Z or Y
-  int32_t ny4;     // number of Y factors mod 4
-  int32_t pad;
-  double coeff;
-};
 hipError_t launch_expect_group(bool dbl, const void* psi, int n, uint64_t flip, const PauliTermDev* terms,
                                int nterms, double* partials, hipStream_t s);
 // lambda = sum_g sum_t c_t P_t psi over all groups (adjoint seed H psi)

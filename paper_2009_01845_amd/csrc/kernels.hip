@@ -922,34 +922,49 @@ __device__ __forceinline__ double rgrad_any(const C* ps, const C* la, int k, uin
   }
 }
 
-template <typename R, bool TWO, int NLD>
-__global__ __launch_bounds__(256) void k_tile2(
-    typename CT<R>::C* __restrict__ psi, typename CT<R>::C* __restrict__ lam, const PassGeom g,
+// LDS scratch of a staged pass (besides the tile itself)
+struct PassSmem {
+  uint64_t hoff[128];
+  double phA[kMaxPhasePerPass];
+  double phNu[kMaxPhasePerPass][kMaxTileBits];
+  double phA0[kMaxPhasePerPass];
+  double phNu0[kMaxPhasePerPass][kMaxTileBits];
+  double phCk[kMaxPhasePerPass][kMaxKBits];
+  int hb[kMaxTileBits];
+  int kpos[kMaxKBits];
+};
+
+// One staged pass over tiles t_first, t_first + t_step, ... < ntiles; the
+// tile-index bits above gbits are the "k bits" of the phase tables.  GUARD:
+// tiles may be smaller than one full sweep of the workgroup.  Gradient
+// partials go to gpart[gslot * gstride + gcol + wave].
+template <typename R, bool TWO, int NLD, bool GUARD>
+__device__ __forceinline__ void pass_body(
+    typename CT<R>::C* __restrict__ psi, typename CT<R>::C* __restrict__ lam, const PassGeom& g,
     const TileOp* __restrict__ ops, const StageRec* __restrict__ stages,
     const typename CT<R>::C* __restrict__ matc, const PhaseRec* __restrict__ phases,
     const int32_t* __restrict__ phlist, const double* __restrict__ dpool, const double* __restrict__ btab,
     const typename CT<R>::C* __restrict__ qtab, const double* __restrict__ qang,
-    const double* __restrict__ scales, double* __restrict__ gpart, int64_t ntiles) {
+    const double* __restrict__ scales, double* __restrict__ gpart, int64_t gstride, int gcol,
+    int64_t t_first, int64_t t_step, int64_t ntiles, int gbits, PassSmem& sm, char* smem) {
   using C = typename CT<R>::C;
   using VT = typename CT<R>::V;
   constexpr int VW = CT<R>::VW;
-  extern __shared__ __align__(16) char smem[];
   const int M = 1 << g.m;
   C* t1 = reinterpret_cast<C*>(smem);
   C* t2 = TWO ? t1 + M : nullptr;
-  __shared__ uint64_t hoff[128];
-  __shared__ double phA[kMaxPhasePerPass];
-  __shared__ double phNu[kMaxPhasePerPass][kMaxTileBits];
-  __shared__ double phA0[kMaxPhasePerPass];
-  __shared__ double phNu0[kMaxPhasePerPass][kMaxTileBits];
-  __shared__ double phCk[kMaxPhasePerPass][kMaxKBits];
-  __shared__ int hb[kMaxTileBits];
-  __shared__ int kpos[kMaxKBits];
+  uint64_t* hoff = sm.hoff;
+  auto& phA = sm.phA;
+  auto& phNu = sm.phNu;
+  auto& phA0 = sm.phA0;
+  auto& phNu0 = sm.phNu0;
+  auto& phCk = sm.phCk;
+  int* hb = sm.hb;
+  int* kpos = sm.kpos;
 
   const int tid = threadIdx.x;
   const int L = g.L, H = g.H, m = g.m, n = g.n;
   const int nph = g.nph, ph0 = g.ph0, nst = g.nst, st0 = g.st0, op0 = g.op0;
-  const int gbits = __builtin_ctz(gridDim.x);   // the grid is a power of two
   const int kb = (n - m) - gbits;
   if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
   if (tid == 0) {  // global positions of the tile-index bits above the grid
@@ -984,7 +999,7 @@ __global__ __launch_bounds__(256) void k_tile2(
   // phase polynomials, part fixed for this workgroup (tile t0 = blockIdx.x,
   // k bits zero): constant, tile-bit coefficients and k-bit coefficients
   {
-    const uint64_t base0 = tbase(blockIdx.x);
+    const uint64_t base0 = tbase(t_first);
     for (int idx = tid; idx < nph * 32; idx += blockDim.x) {
       const int p = idx >> 5, r = idx & 31;
       const PhaseRec rec = phases[phlist[ph0 + p]];
@@ -1014,16 +1029,19 @@ __global__ __launch_bounds__(256) void k_tile2(
     __syncthreads();
   }
 
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (int64_t t = t_first; t < ntiles; t += t_step) {
     const uint64_t base = tbase(t);
     for (int half = 0; half < (TWO ? 2 : 1); ++half) {
       const C* src = half ? lam : psi;
       C* dst = half ? t2 : t1;
       VT buf[NLD];  // issue every load of the tile before the first LDS write
 #pragma unroll
-      for (int u = 0; u < NLD; ++u) buf[u] = *reinterpret_cast<const VT*>(src + gaddr(base, u));
+      for (int u = 0; u < NLD; ++u)
+        if (!GUARD || (u * (int)blockDim.x + tid) * VW < M) buf[u] = *reinterpret_cast<const VT*>(src + gaddr(base, u));
 #pragma unroll
-      for (int u = 0; u < NLD; ++u) *reinterpret_cast<VT*>(dst + swz<R>((u * (int)blockDim.x + tid) * VW)) = buf[u];
+      for (int u = 0; u < NLD; ++u)
+        if (!GUARD || (u * (int)blockDim.x + tid) * VW < M)
+          *reinterpret_cast<VT*>(dst + swz<R>((u * (int)blockDim.x + tid) * VW)) = buf[u];
     }
     // per-tile coefficients of the pass's phase polynomials (the part of theta
     // fixed by the bits outside the tile) from the workgroup part and the k bits
@@ -1059,7 +1077,8 @@ __global__ __launch_bounds__(256) void k_tile2(
         return ((e & 1) ? rm0 : 0u) | ((e & 2) ? rm1 : 0u) | ((e & 4) ? rm2 : 0u) | ((e & 8) ? rm3 : 0u);
       };
       for (int gb = 0; gb < (M >> NR); gb += blockDim.x) {
-        const uint32_t jg = insert_zeros((uint32_t)(gb + tid), st.rbmask);
+        const bool valid = !GUARD || gb + tid < (M >> NR);
+        const uint32_t jg = valid ? insert_zeros((uint32_t)(gb + tid), st.rbmask) : 0u;
         C v[NE], w[NE];
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
@@ -1069,15 +1088,14 @@ __global__ __launch_bounds__(256) void k_tile2(
         for (int oi = 0; oi < st.nops; ++oi) {
           const int o = op0 + st.op0 + (TWO ? st.nops - 1 - oi : oi);
           const int kind = ops[o].kind;
-          const bool act = ((base & ops[o].cout) == ops[o].cout) && ((jg & ops[o].cin) == ops[o].cin);
+          const bool act = valid && ((base & ops[o].cout) == ops[o].cout) && ((jg & ops[o].cin) == ops[o].cin);
           const uint32_t creg = ops[o].creg;
           if (kind == OP_DENSE1 || kind == OP_ROT) {
             const int k = ops[o].b[0];
             if (TWO && kind == OP_ROT && ops[o].gslot >= 0) {
               double pg = act ? rgrad_any(v, w, k, creg, ops[o].pauli) : 0.0;
               for (int off = 32; off > 0; off >>= 1) pg += __shfl_xor(pg, off, 64);
-              if ((tid & 63) == 0)
-                gpart[(int64_t)ops[o].gslot * kGradStride + blockIdx.x * 4 + (tid >> 6)] += pg;
+              if ((tid & 63) == 0) gpart[(int64_t)ops[o].gslot * gstride + gcol + (tid >> 6)] += pg;
             }
             if (!act) continue;
             const C* mp = matc + ops[o].mat + (TWO ? 4 : 0);
@@ -1160,10 +1178,12 @@ __global__ __launch_bounds__(256) void k_tile2(
             apply(12, f12); apply(13, f13); apply(14, f14); apply(15, f15);
           }
         }
+        if (valid) {
 #pragma unroll
-        for (int e = 0; e < NE; ++e) {
-          t1[swz<R>(jg | jr(e))] = v[e];
-          if (TWO) t2[swz<R>(jg | jr(e))] = w[e];
+          for (int e = 0; e < NE; ++e) {
+            t1[swz<R>(jg | jr(e))] = v[e];
+            if (TWO) t2[swz<R>(jg | jr(e))] = w[e];
+          }
         }
       }
       __syncthreads();
@@ -1174,9 +1194,120 @@ __global__ __launch_bounds__(256) void k_tile2(
       const C* src = half ? t2 : t1;
       VT buf[NLD];
 #pragma unroll
-      for (int u = 0; u < NLD; ++u) buf[u] = *reinterpret_cast<const VT*>(src + swz<R>((u * (int)blockDim.x + tid) * VW));
+      for (int u = 0; u < NLD; ++u)
+        if (!GUARD || (u * (int)blockDim.x + tid) * VW < M)
+          buf[u] = *reinterpret_cast<const VT*>(src + swz<R>((u * (int)blockDim.x + tid) * VW));
 #pragma unroll
-      for (int u = 0; u < NLD; ++u) *reinterpret_cast<VT*>(dstg + gaddr(base, u)) = buf[u];
+      for (int u = 0; u < NLD; ++u)
+        if (!GUARD || (u * (int)blockDim.x + tid) * VW < M) *reinterpret_cast<VT*>(dstg + gaddr(base, u)) = buf[u];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename R, bool TWO, int NLD>
+__global__ __launch_bounds__(256) void k_tile2(
+    typename CT<R>::C* __restrict__ psi, typename CT<R>::C* __restrict__ lam, const PassGeom g,
+    const TileOp* __restrict__ ops, const StageRec* __restrict__ stages,
+    const typename CT<R>::C* __restrict__ matc, const PhaseRec* __restrict__ phases,
+    const int32_t* __restrict__ phlist, const double* __restrict__ dpool, const double* __restrict__ btab,
+    const typename CT<R>::C* __restrict__ qtab, const double* __restrict__ qang,
+    const double* __restrict__ scales, double* __restrict__ gpart, int64_t ntiles) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ PassSmem sm;
+  pass_body<R, TWO, NLD, false>(psi, lam, g, ops, stages, matc, phases, phlist, dpool, btab, qtab, qang, scales,
+                                gpart, kGradStride, blockIdx.x * 4, blockIdx.x, gridDim.x, ntiles,
+                                __builtin_ctz(gridDim.x), sm, smem);
+}
+
+// matrices of a rotation exp(-i theta P/2) (slot 0..3) and of its inverse (4..7)
+template <typename C>
+__device__ __forceinline__ void rot_fill(C* m, int pauli, double theta) {
+  double s, c;
+  sincos(0.5 * theta, &s, &c);
+  for (int inv = 0; inv < 2; ++inv) {
+    const double si = inv ? -s : s;
+    C* o = m + 4 * inv;
+    if (pauli == 1) {
+      o[0] = mk<C>(c, 0); o[1] = mk<C>(0, -si); o[2] = mk<C>(0, -si); o[3] = mk<C>(c, 0);
+    } else if (pauli == 2) {
+      o[0] = mk<C>(c, 0); o[1] = mk<C>(-si, 0); o[2] = mk<C>(si, 0); o[3] = mk<C>(c, 0);
+    } else {
+      o[0] = mk<C>(c, -si); o[1] = mk<C>(0, 0); o[2] = mk<C>(0, 0); o[3] = mk<C>(c, si);
+    }
+  }
+}
+
+template <typename R, int NLD>
+__global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
+  using C = typename CT<R>::C;
+  extern __shared__ __align__(16) char smem[];
+  __shared__ PassSmem sm;
+  __shared__ int cur;
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  C* matc = reinterpret_cast<C*>(a.dp.matc);
+  const C* qtab = reinterpret_cast<const C*>(a.dp.qtab);
+  for (;;) {
+    if (tid == 0) cur = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int i = cur;
+    __syncthreads();
+    if (i >= a.count) break;  // every workgroup leaves once the queue is drained
+    const BatchInst in = a.insts[a.order[i]];
+    C* psi = reinterpret_cast<C*>(a.states) + in.state_off;
+    C* lam = reinterpret_cast<C*>(a.states) + in.lam_off;
+    const int64_t N = 1ll << in.n;
+    const double* par = a.params + in.param_base;
+    for (int o = tid; o < in.nops; o += blockDim.x) {
+      const TileOp op = a.dp.ops[in.ops_base + o];
+      if (op.kind == OP_ROT && op.mat >= 0) rot_fill(matc + in.mat_base + op.mat, op.pauli, par[op.pidx]);
+    }
+    for (int64_t x = tid; x < N; x += blockDim.x) psi[x] = mk<C>(x == 0 ? 1.0 : 0.0, 0.0);
+    double* gp = a.gpart + (int64_t)in.slot_base * 4;
+    for (int j = tid; j < in.nslots * 4; j += blockDim.x) gp[j] = 0.0;
+    __syncthreads();
+    for (int dir = 0; dir < 2; ++dir) {
+      if (dir == 1) {
+        // energy of the diagonal observable and lambda = H psi
+        double acc = 0.0;
+        for (int64_t x = tid; x < N; x += blockDim.x) {
+          double d = 0.0;
+          for (int t = 0; t < in.obs_nterms; ++t) {
+            const PauliTermDev T = a.terms[in.obs_off + t];
+            d += (__popcll((uint64_t)x & T.zy) & 1) ? -T.coeff : T.coeff;
+          }
+          const C v = psi[x];
+          acc += d * ((double)v.x * v.x + (double)v.y * v.y);
+          lam[x] = mk<C>(d * v.x, d * v.y);
+        }
+        const double e = block_sum(acc, red);
+        if (tid == 0) a.energies[a.order[i]] = e;
+        __syncthreads();
+      }
+      for (int k = 0; k < in.npass; ++k) {
+        const PassGeom& g = a.geoms[in.pass0 + (dir ? in.npass - 1 - k : k)];
+        const int64_t nt = 1ll << (g.n - g.m);
+        if (dir == 0)
+          pass_body<R, false, NLD, true>(psi, nullptr, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
+                                         matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
+                                         a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
+                                         a.dp.qang + in.qt_base, nullptr, gp, 4, 0, 0, 1, nt, 0, sm, smem);
+        else
+          pass_body<R, true, NLD, true>(psi, lam, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
+                                        matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
+                                        a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
+                                        a.dp.qang + in.qt_base, nullptr, gp, 4, 0, 0, 1, nt, 0, sm, smem);
+      }
+    }
+    // gradient of every parameter, slots in order (deterministic)
+    if (tid == 0) {
+      double* gr = a.grads + in.param_base;
+      for (int j = 0; j < in.nparams; ++j) gr[j] = 0.0;
+      for (int sl = 0; sl < in.nslots; ++sl) {
+        const int pidx = a.slot_pidx[in.slot_base + sl];
+        if (pidx >= 0) gr[pidx] += gp[sl * 4] + gp[sl * 4 + 1] + gp[sl * 4 + 2] + gp[sl * 4 + 3];
+      }
     }
     __syncthreads();
   }
@@ -1337,6 +1468,16 @@ hipError_t perm_launch(int nld, void* psi, const PassGeom& g, const PermArgs& pa
     case 8: return perm_launch_t<R, 8>(psi, g, pa, nt, grid, lds, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_batch(bool dbl, const BatchArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  const size_t lds = (size_t(1) << 12) * (dbl ? 16 : 8) * 2;  // two tiles of up to 2^12 amplitudes
+  hipError_t e = dbl ? set_lds_fn((void*)k_batch<double, 16>, lds) : set_lds_fn((void*)k_batch<float, 8>, lds);
+  if (e != hipSuccess) return e;
+  if (dbl) hipLaunchKernelGGL((k_batch<double, 16>), dim3(a.grid), dim3(kThreads), lds, s, a);
+  else hipLaunchKernelGGL((k_batch<float, 8>), dim3(a.grid), dim3(kThreads), lds, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* tau, hipStream_t s) {

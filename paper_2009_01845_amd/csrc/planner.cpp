@@ -328,7 +328,7 @@ void stage_pass(Plan& plan, Pass& ps) {
   PassGeom& g = ps.geom;
   g.kern = 1;
   g.st0 = g.nst = g.ph0 = g.nph = 0;
-  if (g.m < 12) return;
+  if (g.m < (plan.force_stage ? kRegBits + 1 : 12)) return;
   int nph = 0;
   for (const TileOp& op : ps.ops) {
     if (op.kind == OP_DENSEK) return;  // k >= 3 matrices keep the one-sweep-per-op kernel
@@ -468,7 +468,7 @@ void stage_pass(Plan& plan, Pass& ps) {
         // tile-index bits above gb ("k bits") sit at global positions kp[j]
         {
           const int ntb = n - g.m;
-          const int gb = std::min(ntb, kGridBits);
+          const int gb = std::min(ntb, plan.grid_bits);
           const int kb = ntb - gb;
           if (kb > kMaxKBits) throw std::runtime_error("planner: too many tile-index bits");
           std::vector<int> kp;
@@ -628,6 +628,8 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
   plan.dbl = dbl;
   plan.nparams = C.nparams;
   plan.ngates = (int)C.gates.size();
+  plan.grid_bits = opts.grid_bits;
+  plan.force_stage = opts.force_stage;
   int m, L;
   default_tile(n, dbl, opts, &m, &L);
   const int Hmax = m - L;

@@ -26,6 +26,8 @@ struct TuneOpts {
   int fuse_k = 0;
   int use_mfma = -1;
   int low_bits = 0;
+  int grid_bits = kGridBits;  // log2 of the workgroups walking a pass's tiles (0: one workgroup)
+  bool force_stage = false;   // register-blocked stages also for tiles below 2^12
 };
 
 enum PassKind : int { PASS_TILE = 1, PASS_PHASE = 2, PASS_PERM = 3, PASS_MFMA = 4, PASS_DENSE = 5 };
@@ -61,6 +63,8 @@ struct Plan {
   int nparams = 0;
   int ngates = 0;
   int ngrad_slots = 0;           // ops carrying a trainable parameter
+  int grid_bits = kGridBits;
+  bool force_stage = false;
 };
 
 // Circuit description kept by the C ABI.
