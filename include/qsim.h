@@ -209,10 +209,13 @@ qs_status qs_batch_destroy(qs_batch* b);
 
 /* ------------------------------------------------------------------- tuner
  * Time the candidate plans (tile width, fusion width, MFMA on/off) of c on
- * state s, keep the fastest whose result agrees with the default plan, and
- * compile c with it.  cache_path (may be NULL) is a text file of previous
- * choices keyed by (n, gate count, dtype, device); it is read first and
- * appended to. The state's contents are destroyed. */
+ * state s, keep the fastest whose result from |+...+> agrees with the
+ * default plan's (2-norm distance below 1e-4 for complex64, 1e-9 for
+ * complex128), and compile c with it.  cache_path (may be NULL) is a text
+ * file of previous choices, one line per key (n, gate count, dtype, device
+ * architecture, 64-bit hash of the gate list); a hit skips the timing, a miss
+ * appends a line.  Needs one extra state-sized device buffer while it runs.
+ * The state's contents are destroyed. */
 qs_status qs_autotune(qs_circuit* c, qs_state* s, const double* params, const char* cache_path);
 
 /* --------------------------------------------------------------- profiling

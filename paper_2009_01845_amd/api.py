@@ -364,6 +364,10 @@ class Circuit:
     def run(self, st: State, params=None):
         circuit_run(self.h, st.h, params)
 
+    def autotune(self, st: State, params=None, cache_path: str | None = None):
+        """Pick the fastest plan for this circuit on st's precision (st is overwritten)."""
+        autotune(self.h, st.h, params, cache_path)
+
     def info(self):
         return circuit_info(self.h)
 

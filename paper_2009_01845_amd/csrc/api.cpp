@@ -318,6 +318,12 @@ void run_passes(const DevPlanBuf& dp, const Plan& plan, bool dbl, void* psi, voi
       ProfScope pr(2, s);
       hipck(launch_perm_pass(dbl, psi, ps.geom, ps.sigma.data(), s), "perm pass");
       if (lam) hipck(launch_perm_pass(dbl, lam, ps.geom, ps.sigma.data(), s), "perm pass");
+    } else if (ps.kind == PASS_MFMA) {
+      ProfScope pr(3, s);
+      const TileOp& op = ps.ops[0];
+      const double* m = dp.view.mat + 2 * (op.mat + (lam ? (1 << (2 * op.k)) : 0));
+      hipck(launch_mfma_pass(dbl, psi, ps.geom, op.b, op.k, m, s), "mfma pass");
+      if (lam) hipck(launch_mfma_pass(dbl, lam, ps.geom, op.b, op.k, m, s), "mfma pass");
     } else {
       ProfScope pr(lam ? 7 : 0, s);
       hipck(launch_tile_pass(dbl, psi, lam, dp.geoms[i], dp.view, params, scales, gpart, s), "tile pass");
@@ -1160,11 +1166,179 @@ qs_status qs_batch_destroy(qs_batch* b) {
   });
 }
 
-qs_status qs_autotune(qs_circuit* c, qs_state* s, const double*, const char*) {
+namespace {
+
+// FNV-1a over everything that defines the circuit's action.
+uint64_t circuit_hash(const HostCircuit& hc) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t nb) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < nb; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(&hc.n, sizeof hc.n);
+  for (const Gate& g : hc.gates) {
+    mix(&g.k, sizeof g.k);
+    mix(g.tq, sizeof(int) * g.k);
+    for (int q : g.cq) mix(&q, sizeof q);
+    mix(&g.is_rot, sizeof g.is_rot);
+    mix(&g.pauli, sizeof g.pauli);
+    mix(&g.pidx, sizeof g.pidx);
+    if (!g.mat.empty()) mix(g.mat.data(), g.mat.size() * sizeof(g.mat[0]));
+  }
+  return h;
+}
+
+struct TuneChoice {
+  int tile_bits, fuse_k, use_mfma, low_bits;
+};
+
+std::string tune_key(const qs_circuit* c, const qs_state* s) {
+  int dev = 0;
+  hipck(hipGetDevice(&dev), "hipGetDevice");
+  hipDeviceProp_t pr;
+  hipck(hipGetDeviceProperties(&pr, dev), "hipGetDeviceProperties");
+  std::string arch(pr.gcnArchName);
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "n=%d gates=%zu dtype=%s device=%s hash=%016llx", c->hc.n, c->hc.gates.size(),
+                s->dbl() ? "c128" : "c64", arch.c_str(), (unsigned long long)circuit_hash(c->hc));
+  return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, TuneChoice* out) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    const size_t kl = key.size();
+    if (std::strncmp(line, key.c_str(), kl) != 0 || line[kl] != ' ') continue;
+    TuneChoice t;
+    if (std::sscanf(line + kl, " tile_bits=%d fuse_k=%d use_mfma=%d low_bits=%d", &t.tile_bits, &t.fuse_k,
+                    &t.use_mfma, &t.low_bits) == 4) {
+      *out = t;  // the last matching line wins
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_append(const char* path, const std::string& key, const TuneChoice& t, double ms) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) fail(QS_E_INVALID, std::string("cannot open tuning cache ") + path);
+  std::fprintf(f, "%s tile_bits=%d fuse_k=%d use_mfma=%d low_bits=%d ms=%.4f\n", key.c_str(), t.tile_bits, t.fuse_k,
+               t.use_mfma, t.low_bits, ms);
+  std::fclose(f);
+}
+
+void compile_with(qs_circuit* c, const TuneChoice& t, bool dbl, hipStream_t s) {
+  TuneOpts o;
+  o.tile_bits = t.tile_bits;
+  o.fuse_k = t.fuse_k;
+  o.use_mfma = t.use_mfma;
+  o.low_bits = t.low_bits;
+  c->hc.opts = o;
+  c->planned = false;
+  c->dev_ok = false;
+  ensure_plan(c, dbl, s);
+}
+
+}  // namespace
+
+// Candidates: the default plan first (it is the reference every other
+// candidate is checked against), then fusion widths with and without matrix
+// cores, then narrower tiles.  Each is timed over a few runs from |+...+>.
+qs_status qs_autotune(qs_circuit* c, qs_state* s, const double* params, const char* cache_path) {
   return guard([&] {
     if (!c) fail(QS_E_INVALID, "null circuit");
     check_state(s);
-    fail(QS_E_UNSUPPORTED, "autotuner is not built yet");
+    if (c->hc.n != s->n) fail(QS_E_STATE, "circuit and state sizes differ");
+    if (c->hc.nparams > 0 && !params) fail(QS_E_INVALID, "circuit has parameters but params is null");
+    const bool dbl = s->dbl();
+    const std::string key = tune_key(c, s);
+    TuneChoice hit;
+    if (cache_lookup(cache_path, key, &hit)) {
+      compile_with(c, hit, dbl, s->stream);
+      return;
+    }
+    const double* dpar = nullptr;
+    if (c->hc.nparams > 0) {
+      c->dparams.ensure(sizeof(double) * c->hc.nparams);
+      hipck(hipMemcpyAsync(c->dparams.p, params, sizeof(double) * c->hc.nparams, hipMemcpyHostToDevice, s->stream),
+            "params upload");
+      dpar = c->dparams.as<double>();
+    }
+    std::vector<TuneChoice> cands = {{0, 0, -1, 0}, {0, 2, -1, 0}, {0, 3, 0, 0}, {0, 4, 0, 0},
+                                     {0, 4, 1, 0},  {0, 5, 0, 0},  {0, 5, 1, 0}, {11, 0, -1, 0},
+                                     {10, 0, -1, 0}};
+    DBuf ref;
+    ref.ensure(s->bytes());
+    double* part = scratch_doubles(s, kGridMax + 8);
+    hipEvent_t e0, e1;
+    hipck(hipEventCreate(&e0), "hipEventCreate");
+    hipck(hipEventCreate(&e1), "hipEventCreate");
+    struct EvFree {
+      hipEvent_t a, b;
+      ~EvFree() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } evfree{e0, e1};
+    const double tol = dbl ? 1e-9 : 1e-4;  // on the 2-norm distance to the default plan's result
+    double ref_n2 = 0, best_ms = 1e300;
+    TuneChoice best = cands[0];
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      const TuneChoice& t = cands[ci];
+      TuneOpts o;
+      o.tile_bits = t.tile_bits;
+      o.fuse_k = t.fuse_k;
+      o.use_mfma = t.use_mfma;
+      o.low_bits = t.low_bits;
+      Plan p;
+      try {
+        p = plan_circuit(c->hc, o, dbl);
+      } catch (const std::exception&) {
+        if (ci == 0) throw;
+        continue;  // this tiling does not fit the circuit
+      }
+      DevPlanBuf dp;
+      dp.load(p, s->stream);
+      hipck(launch_set_plus(dbl, s->ptr, s->n, s->stream), "set_plus");
+      run_passes(dp, p, dbl, s->ptr, nullptr, dpar, nullptr, nullptr, s->stream);
+      if (ci == 0) {
+        hipck(hipMemcpyAsync(ref.p, s->ptr, s->bytes(), hipMemcpyDeviceToDevice, s->stream), "copy");
+        hipck(launch_sumsq(dbl, ref.p, s->n, part, s->stream), "norm");
+        ref_n2 = download_scalar(part + kGridMax, s->stream);
+      } else {
+        // |a - b|^2 = |a|^2 + |b|^2 - 2 Re<a|b>
+        hipck(launch_sumsq(dbl, s->ptr, s->n, part, s->stream), "norm");
+        const double n2 = download_scalar(part + kGridMax, s->stream);
+        hipck(launch_dot_re(dbl, ref.p, s->ptr, s->n, part, s->stream), "dot");
+        const double d2 = ref_n2 + n2 - 2 * download_scalar(part + kGridMax, s->stream);
+        if (!(d2 < tol * tol)) continue;
+      }
+      double ms = 1e300;
+      for (int rep = 0; rep < 3; ++rep) {
+        hipck(launch_set_plus(dbl, s->ptr, s->n, s->stream), "set_plus");
+        hipck(hipEventRecord(e0, s->stream), "hipEventRecord");
+        run_passes(dp, p, dbl, s->ptr, nullptr, dpar, nullptr, nullptr, s->stream);
+        hipck(hipEventRecord(e1, s->stream), "hipEventRecord");
+        hipck(hipEventSynchronize(e1), "hipEventSynchronize");
+        float f = 0;
+        hipck(hipEventElapsedTime(&f, e0, e1), "hipEventElapsedTime");
+        ms = std::min(ms, (double)f);
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+    compile_with(c, best, dbl, s->stream);
+    cache_append(cache_path, key, best, best_ms);
   });
 }
 

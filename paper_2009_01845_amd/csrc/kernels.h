@@ -77,6 +77,11 @@ hipError_t launch_batch(bool dbl, const BatchArgs& a, hipStream_t s);
 // Fill the forward and inverse matrices of every rotation op from params.
 hipError_t launch_rot_mats(bool dbl, const DevPlan& dp, const double* params, hipStream_t s);
 hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* tau, hipStream_t s);
+// Dense k-qubit block (k = 3..5) with matrix-core instructions; the tile is the
+// targets plus the 7 lowest other bits (g.m == k + 7); tl[t] = tile-local
+// position of target t; mat = 2^k x 2^k complex128 (device).
+hipError_t launch_mfma_pass(bool dbl, void* psi, const PassGeom& g, const int* tl, int k, const double* mat,
+                            hipStream_t s);
 
 hipError_t launch_set_basis(bool dbl, void* psi, int n, uint64_t x, hipStream_t s);
 hipError_t launch_set_plus(bool dbl, void* psi, int n, hipStream_t s);

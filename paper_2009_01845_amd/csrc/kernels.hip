@@ -1220,6 +1220,145 @@ __global__ __launch_bounds__(256) void k_tile2(
                                 __builtin_ctz(gridDim.x), sm, smem);
 }
 
+// ----------------------------------------------------------------------------
+// dense k-qubit block (k = 3..5) on matrix cores.  A tile holds the 2^k target
+// values of 128 columns (the 7 lowest non-target bits); with the gate realified
+// as GR = [[Gr, -Gi], [Gi, Gr]] (2^(k+1) square) every column is updated by one
+// real product [Yr; Yi] = GR [Xr; Xi].  v_mfma_*_16x16x4: A is 16x4 (lane l
+// holds row l%16, column l/16), B is 4x16 (row l/16, column l%16), D is 16x16
+// with column l%16 and row 4*(l/16)+v (f32) or 4*v+l/16 (f64) in element v.
+// ----------------------------------------------------------------------------
+struct MfmaArgs {
+  int tl[5];  // tile-local position of target t (t = 0 is the matrix MSB)
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct MfmaT;
+template <> struct MfmaT<float> {
+  using Acc = f32x4;
+  static __device__ __forceinline__ Acc mma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output row held in accumulator element v (column = lane % 16)
+  static __device__ __forceinline__ int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct MfmaT<double> {
+  using Acc = f64x4;
+  static __device__ __forceinline__ Acc mma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // the f64 form interleaves its output rows across the four lane groups
+  static __device__ __forceinline__ int out_row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+
+template <typename R, int K, int NLD>
+__global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ psi, const PassGeom g,
+                                              const MfmaArgs ma, const double* __restrict__ mat, int64_t ntiles) {
+  using C = typename CT<R>::C;
+  using VT = typename CT<R>::V;
+  using Acc = typename MfmaT<R>::Acc;
+  constexpr int VW = CT<R>::VW;
+  constexpr int D = 1 << K;      // complex dimension
+  constexpr int DR = 2 * D;      // realified dimension
+  constexpr int RB = DR / 16;    // 16-row blocks of the output
+  constexpr int KS = DR / 4;     // 4-deep steps of the contraction
+  constexpr int NCOL = 128;      // columns per tile
+  extern __shared__ __align__(16) char smem[];
+  C* tile = reinterpret_cast<C*>(smem);
+  __shared__ uint32_t rowoff[D];
+  __shared__ uint32_t coloff[NCOL];
+  __shared__ uint64_t hoff[128];
+  __shared__ int hb[kMaxTileBits];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int L = g.L, H = g.H, m = g.m;
+  if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
+  __syncthreads();
+  for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
+    uint64_t off = 0;
+    for (int i = 0; i < H; ++i)
+      if ((hc >> i) & 1) off |= 1ull << hb[i];
+    hoff[hc] = off;
+  }
+  uint32_t tmask = 0;
+#pragma unroll
+  for (int t = 0; t < K; ++t) tmask |= 1u << ma.tl[t];
+  for (int r = tid; r < D; r += blockDim.x) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      if ((r >> (K - 1 - t)) & 1) o |= 1u << ma.tl[t];
+    rowoff[r] = o;
+  }
+  for (int c = tid; c < NCOL; c += blockDim.x) coloff[c] = insert_zeros((uint32_t)c, tmask);
+  // A fragments of the realified gate, resident for the whole launch
+  R a[RB][KS];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int i = 16 * rb + (lane & 15), j = 4 * ks + (lane >> 4);
+      const int gi = i & (D - 1), gj = j & (D - 1);
+      const double re = mat[2 * (gi * D + gj)], im = mat[2 * (gi * D + gj) + 1];
+      a[rb][ks] = (R)((i < D) == (j < D) ? re : (i < D ? -im : im));
+    }
+  __syncthreads();
+  const uint32_t lomask = (1u << L) - 1u;
+  (void)m;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint64_t base = (uint64_t)t << L;
+    for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
+    VT buf[NLD];
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int e = (u * (int)blockDim.x + tid) * VW;
+      buf[u] = *reinterpret_cast<const VT*>(psi + (base | hoff[e >> L] | (uint64_t)(e & lomask)));
+    }
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int e = (u * (int)blockDim.x + tid) * VW;
+      *reinterpret_cast<VT*>(tile + swz<R>(e)) = buf[u];
+    }
+    __syncthreads();
+    for (int cb = wave; cb < NCOL / 16; cb += (int)(blockDim.x >> 6)) {
+      const uint32_t co = coloff[16 * cb + (lane & 15)];
+      Acc acc[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int row = 4 * ks + (lane >> 4);  // realified row of X
+        const C x = tile[swz<R>(rowoff[row & (D - 1)] | co)];
+        const R bval = row < D ? x.x : x.y;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = MfmaT<R>::mma(a[rb][ks], bval, acc[rb]);
+      }
+      // output row 16*rb + 4*(lane/16) + v: real parts in the first RB/2 blocks,
+      // imaginary parts of the same rows RB/2 blocks later
+#pragma unroll
+      for (int rb = 0; rb < RB / 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * rb + MfmaT<R>::out_row(lane, v);
+          tile[swz<R>(rowoff[row] | co)] = mk<C>(acc[rb][v], acc[rb + RB / 2][v]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int e = (u * (int)blockDim.x + tid) * VW;
+      buf[u] = *reinterpret_cast<const VT*>(tile + swz<R>(e));
+    }
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int e = (u * (int)blockDim.x + tid) * VW;
+      *reinterpret_cast<VT*>(psi + (base | hoff[e >> L] | (uint64_t)(e & lomask))) = buf[u];
+    }
+    __syncthreads();
+  }
+}
+
 // matrices of a rotation exp(-i theta P/2) (slot 0..3) and of its inverse (4..7)
 template <typename C>
 __device__ __forceinline__ void rot_fill(C* m, int pauli, double theta) {
@@ -1468,6 +1607,44 @@ hipError_t perm_launch(int nld, void* psi, const PassGeom& g, const PermArgs& pa
     case 8: return perm_launch_t<R, 8>(psi, g, pa, nt, grid, lds, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename R, int K>
+hipError_t mfma_launch_t(void* psi, const PassGeom& g, const MfmaArgs& ma, const double* mat, hipStream_t s) {
+  constexpr int NLD = (1 << (K + 7)) / (kThreads * CT<R>::VW);
+  const int64_t nt = 1ll << (g.n - g.m);
+  const int grid = (int)(nt < kGridMax ? nt : kGridMax);
+  const size_t lds = (size_t(1) << g.m) * sizeof(typename CT<R>::C);
+  hipError_t e = set_lds_fn((void*)k_mfma<R, K, NLD>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_mfma<R, K, NLD>), dim3(grid), dim3(kThreads), lds, s, (typename CT<R>::C*)psi, g, ma, mat,
+                     nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_pass(bool dbl, void* psi, const PassGeom& g, const int* tl, int k, const double* mat,
+                            hipStream_t s) {
+  // tile = targets + 7 other bits: L may reach 12 when the targets are low bits
+  if (k < 3 || k > 5 || g.m != k + 7 || g.m > g.n || g.n > kMaxQubits) return hipErrorInvalidValue;
+  if (g.L < 7 || g.L > 12 || g.H < 0 || g.H > 5 || g.L + g.H != g.m) return hipErrorInvalidValue;
+  for (int i = 0; i < g.H; ++i)
+    if (g.hbits[i] < g.L || g.hbits[i] >= g.n || (i && g.hbits[i] <= g.hbits[i - 1])) return hipErrorInvalidValue;
+  MfmaArgs ma;
+  uint32_t seen = 0;
+  for (int t = 0; t < 5; ++t) ma.tl[t] = 0;
+  for (int t = 0; t < k; ++t) {
+    if (tl[t] < 0 || tl[t] >= g.m || ((seen >> tl[t]) & 1)) return hipErrorInvalidValue;
+    seen |= 1u << tl[t];
+    ma.tl[t] = tl[t];
+  }
+  if (dbl) {
+    if (k == 3) return mfma_launch_t<double, 3>(psi, g, ma, mat, s);
+    if (k == 4) return mfma_launch_t<double, 4>(psi, g, ma, mat, s);
+    return mfma_launch_t<double, 5>(psi, g, ma, mat, s);
+  }
+  if (k == 3) return mfma_launch_t<float, 3>(psi, g, ma, mat, s);
+  if (k == 4) return mfma_launch_t<float, 4>(psi, g, ma, mat, s);
+  return mfma_launch_t<float, 5>(psi, g, ma, mat, s);
 }
 
 hipError_t launch_batch(bool dbl, const BatchArgs& a, hipStream_t s) {

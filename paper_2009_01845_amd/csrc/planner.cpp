@@ -77,6 +77,7 @@ struct BitGate {
   std::vector<Term> terms;
   uint64_t nmask = 0;  // bits where the gate is not diagonal
   uint64_t dmask = 0;  // bits where it is diagonal (controls, diagonal targets)
+  bool mfma = false;   // applied as a dense block on matrix cores (own pass)
 };
 
 // Pending op inside an open pass, in global bit terms.
@@ -143,8 +144,20 @@ void default_tile(int n, bool dbl, const TuneOpts& o, int* m, int* L) {
 
 namespace {
 
+// (I - Pc) (x) I + Pc (x) G on (controls..., targets...): a controlled gate as
+// one dense matrix, controls as the most significant index bits
+std::vector<cd> expand_controls(const std::vector<cd>& G, int k, int nc) {
+  const int dk = 1 << k, dt = 1 << (k + nc);
+  std::vector<cd> M(size_t(dt) * dt, cd(0, 0));
+  for (int i = 0; i < dt; ++i) M[size_t(i) * dt + i] = 1.0;
+  const int c1 = ((1 << nc) - 1) << k;  // all controls 1
+  for (int r = 0; r < dk; ++r)
+    for (int c = 0; c < dk; ++c) M[size_t(c1 | r) * dt + (c1 | c)] = G[size_t(r) * dk + c];
+  return M;
+}
+
 // Convert a user gate to index bits under the current relabelling.
-BitGate to_bits(const Gate& g, int n, const std::vector<int>& phys) {
+BitGate to_bits(const Gate& g, int n, const std::vector<int>& phys, const TuneOpts& opts) {
   BitGate b;
   b.k = g.k;
   for (int i = 0; i < g.k; ++i) b.tb[i] = phys[g.tq[i]];
@@ -166,6 +179,22 @@ BitGate to_bits(const Gate& g, int n, const std::vector<int>& phys) {
   if (!diag) {
     b.kind = BK_DENSE;
     b.nmask = tmask;
+    const int kt = g.k + (int)g.cq.size();
+    const int kmin = opts.use_mfma > 0 ? 3 : 4;
+    if (opts.use_mfma != 0 && kt >= kmin && kt <= 5 && n >= kt + 7) {
+      // the whole controlled gate becomes one dense block on matrix cores
+      b.mfma = true;
+      if (!g.cq.empty()) {
+        b.mat = expand_controls(g.mat, g.k, (int)g.cq.size());
+        int t = 0;
+        for (int q : g.cq) b.tb[t++] = phys[q];
+        for (int i = 0; i < g.k; ++i) b.tb[t++] = phys[g.tq[i]];
+        b.k = kt;
+        b.nmask = b.cmask | tmask;
+        b.dmask = 0;
+        b.cmask = 0;
+      }
+    }
     return b;
   }
   b.dmask |= tmask;
@@ -594,6 +623,146 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
   hsel.clear();
 }
 
+// Matrix of gate g (targets then controls, all inside `sup`) on the qubit
+// list sup (sup[0] = most significant matrix bit).
+std::vector<cd> embed_gate(const Gate& g, const std::vector<int>& sup) {
+  const int w = (int)sup.size(), dim = 1 << w, dk = 1 << g.k;
+  auto bitpos = [&](int q) { return w - 1 - int(std::find(sup.begin(), sup.end(), q) - sup.begin()); };
+  std::vector<int> tp(g.k), cp;
+  for (int t = 0; t < g.k; ++t) tp[t] = bitpos(g.tq[t]);
+  for (int q : g.cq) cp.push_back(bitpos(q));
+  std::vector<cd> M(size_t(dim) * dim, cd(0, 0));
+  for (int x = 0; x < dim; ++x) {
+    bool on = true;
+    for (int c : cp) on &= ((x >> c) & 1) != 0;
+    if (!on) {
+      M[size_t(x) * dim + x] = 1.0;
+      continue;
+    }
+    int col = 0, rest = x;
+    for (int t = 0; t < g.k; ++t) {
+      col = (col << 1) | ((x >> tp[t]) & 1);
+      rest &= ~(1 << tp[t]);
+    }
+    for (int r = 0; r < dk; ++r) {
+      int y = rest;
+      for (int t = 0; t < g.k; ++t)
+        if ((r >> (g.k - 1 - t)) & 1) y |= 1 << tp[t];
+      M[size_t(y) * dim + x] += g.mat[size_t(r) * dk + col];
+    }
+  }
+  return M;
+}
+
+}  // namespace
+
+// Greedy fusion (the paper's circuit.fuse() of Sec. 2.4.5, widened to K
+// qubits): consecutive fixed gates are multiplied into one dense matrix while
+// their joint support stays within K qubits; rotations with run-time angles
+// end a block and pass through.
+std::vector<Gate> fuse_gates(const std::vector<Gate>& in, int K) {
+  std::vector<Gate> out;
+  std::vector<int> sup;
+  std::vector<cd> U;
+  std::vector<const Gate*> members;
+  auto flush = [&]() {
+    if (members.size() == 1) out.push_back(*members[0]);
+    else if (!members.empty()) {
+      Gate f;
+      f.k = (int)sup.size();
+      for (int i = 0; i < f.k; ++i) f.tq[i] = sup[i];
+      f.mat = U;
+      out.push_back(f);
+    }
+    members.clear();
+    sup.clear();
+    U.clear();
+  };
+  for (const Gate& g : in) {
+    if (g.is_rot) {
+      flush();
+      out.push_back(g);
+      continue;
+    }
+    std::vector<int> gs(g.tq, g.tq + g.k);
+    gs.insert(gs.end(), g.cq.begin(), g.cq.end());
+    std::vector<int> u = sup;
+    for (int q : gs)
+      if (!has(u, q)) u.push_back(q);
+    if ((int)u.size() > K) {
+      flush();
+      u = gs;
+    }
+    std::sort(u.begin(), u.end());
+    const int dim = 1 << u.size();
+    // re-express the block so far on the grown support, then apply g
+    std::vector<cd> prev(size_t(dim) * dim, cd(0, 0));
+    if (members.empty()) {
+      for (int i = 0; i < dim; ++i) prev[size_t(i) * dim + i] = 1.0;
+    } else {
+      Gate blk;
+      blk.k = (int)sup.size();
+      for (int i = 0; i < blk.k; ++i) blk.tq[i] = sup[i];
+      blk.mat = U;
+      prev = embed_gate(blk, u);
+    }
+    U = matmul(embed_gate(g, u), prev, dim);
+    sup = u;
+    members.push_back(&g);
+    if (sup.size() > 5) throw std::runtime_error("fusion support exceeds 5 qubits");
+  }
+  flush();
+  return out;
+}
+
+namespace {
+
+// A dense block on matrix cores: tile = targets + the 7 lowest other bits.
+void add_mfma_pass(Plan& plan, int n, const BitGate& b) {
+  Pass ps;
+  ps.kind = PASS_MFMA;
+  uint64_t tm = 0;
+  for (int t = 0; t < b.k; ++t) tm |= 1ull << b.tb[t];
+  int L = 0, nonT = 0;
+  while (nonT < 7) {
+    if (!((tm >> L) & 1)) ++nonT;
+    ++L;
+  }
+  PassGeom& g = ps.geom;
+  std::memset(&g, 0, sizeof(g));
+  g.n = n;
+  g.L = L;
+  int h = 0;
+  for (int t = 0; t < b.k; ++t)
+    if (b.tb[t] >= L) ++h;
+  std::vector<int> hs;
+  for (int t = 0; t < b.k; ++t)
+    if (b.tb[t] >= L) hs.push_back(b.tb[t]);
+  std::sort(hs.begin(), hs.end());
+  g.H = h;
+  g.m = L + h;
+  for (int i = 0; i < h; ++i) g.hbits[i] = hs[i];
+  g.kern = 0;
+  TileOp op;
+  std::memset(&op, 0, sizeof(op));
+  op.kind = OP_MFMA;
+  op.k = b.k;
+  op.gslot = -1;
+  op.pidx = -1;
+  op.aux = -1;
+  for (int t = 0; t < b.k; ++t) {
+    const int bit = b.tb[t];
+    op.b[t] = bit < L ? bit : L + (int)(std::find(hs.begin(), hs.end(), bit) - hs.begin());
+  }
+  const int dim = 1 << b.k;
+  op.mat = (int)plan.matpool.size();
+  plan.matpool.insert(plan.matpool.end(), b.mat.begin(), b.mat.end());
+  std::vector<cd> inv = dagger(b.mat, dim);
+  plan.matpool.insert(plan.matpool.end(), inv.begin(), inv.end());
+  ps.ops.push_back(op);
+  plan.passes.push_back(ps);
+}
+
 // Involutive bit-permutation pass: data at bit a moves to bit tau[a].
 void add_perm_pass(Plan& plan, int n, int L, bool dbl, const std::vector<int>& tau) {
   bool ident = true;
@@ -634,17 +803,21 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
   default_tile(n, dbl, opts, &m, &L);
   const int Hmax = m - L;
 
+  // 0. optional fusion of consecutive fixed gates into <= fuse_k-qubit blocks
+  const std::vector<Gate> fused = opts.fuse_k >= 2 ? fuse_gates(C.gates, opts.fuse_k) : std::vector<Gate>();
+  const std::vector<Gate>& gates = opts.fuse_k >= 2 ? fused : C.gates;
+
   // 1. relabel SWAPs, convert to index bits
   std::vector<int> phys(n);
   for (int q = 0; q < n; ++q) phys[q] = n - 1 - q;
   std::vector<BitGate> bg;
-  bg.reserve(C.gates.size());
-  for (const Gate& g : C.gates) {
+  bg.reserve(gates.size());
+  for (const Gate& g : gates) {
     if (!g.is_rot && g.k == 2 && g.cq.empty() && is_swap(g.mat)) {
       std::swap(phys[g.tq[0]], phys[g.tq[1]]);
       continue;
     }
-    bg.push_back(to_bits(g, n, phys));
+    bg.push_back(to_bits(g, n, phys, opts));
   }
   const int G = (int)bg.size();
 
@@ -716,6 +889,10 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
           ++placed;
           continue;
         }
+        if (b.mfma) {  // placed between tiled passes below
+          ++it;
+          continue;
+        }
         std::vector<int> need;
         for (int t = 0; t < b.k; ++t) {
           int bit = b.tb[t];
@@ -759,6 +936,21 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
         ++placed;
       }
     }
+    int mg = -1;  // a ready matrix-core block goes next, after this pass
+    for (int g : ready)
+      if (bg[g].mfma) {
+        mg = g;
+        break;
+      }
+    if (mg >= 0) {
+      PhasePoly Q = extract_terms(P, n, bg[mg].nmask, false);
+      if (!Q.empty) {
+        RawOp ro;
+        ro.kind = OP_PHASE;
+        ro.poly = std::move(Q);
+        raw.push_back(std::move(ro));
+      }
+    }
     if (scheduled == G && !P.empty) {
       PhasePoly Q = extract_terms(P, n, ~0ull, true);
       if (!Q.empty) {
@@ -775,8 +967,13 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
       ro.scale_idx = 0;
       raw.push_back(std::move(ro));
     }
-    if (placed == 0 && raw.empty()) throw std::runtime_error("planner: no gate fits a tile");
+    if (placed == 0 && raw.empty() && mg < 0) throw std::runtime_error("planner: no gate fits a tile");
     close_pass(plan, C, m, L, hsel, raw);
+    if (mg >= 0) {
+      add_mfma_pass(plan, n, bg[mg]);
+      auto it = ready.find(mg);
+      finish(mg, it);
+    }
   }
   if (!P.empty) {  // only reachable for an all-diagonal remainder after the loop
     PhasePoly Q = extract_terms(P, n, ~0ull, true);

@@ -95,6 +95,9 @@ PhasePoly ising_poly(int n, const double* J, const double* h);
 // RX(params[0]) on every qubit, optionally followed by exp(i scales[0] E(x)).
 Plan plan_rx_layer(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly);
 
+// Greedy fusion of consecutive fixed gates into blocks of at most K qubits.
+std::vector<Gate> fuse_gates(const std::vector<Gate>& in, int K);
+
 // Named gate matrices (row-major complex); returns k or 0 for an unknown name.
 int named_gate(const std::string& name, double theta, std::vector<cd>& out);
 

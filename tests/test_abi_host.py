@@ -148,3 +148,15 @@ def test_swap_relabel_needs_no_pass_when_undone(api):
     assert api.Circuit.from_spec(n, spec).info()[1] == 0
     spec = [qsynth.gate("SWAP", (0, 5)), qsynth.gate("SWAP", (5, 9))]  # a 3-cycle: two involutions
     assert api.Circuit.from_spec(n, spec).info()[1] == 2
+
+
+def test_dense_blocks_plan_onto_matrix_cores(api):
+    rng = np.random.default_rng(0)
+    spec = [qsynth.gate("MAT", (1, 4, 7, 9), mat=qsynth.haar_unitary(16, rng)),
+            qsynth.gate("MAT", (0, 2, 3), (11,), mat=qsynth.haar_unitary(8, rng))]
+    auto = api.Circuit.from_spec(14, spec)
+    on = api.Circuit.from_spec(14, spec, use_mfma=1)
+    off = api.Circuit.from_spec(14, spec, use_mfma=0)
+    assert [k for k, _, _ in on.passes()].count(4) == 2
+    assert [k for k, _, _ in auto.passes()].count(4) == 2   # k + controls >= 4 by default
+    assert 4 not in [k for k, _, _ in off.passes()]

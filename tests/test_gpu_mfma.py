@@ -1,0 +1,133 @@
+"""Dense 3-5 qubit blocks applied on matrix cores (MFMA) against the oracle."""
+import numpy as np
+import pytest
+
+import qsynth
+from oracle import circuits as ocirc
+
+from gpu_util import TOL, banner, gpu_state, maxabs, oracle_input
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2009_01845_amd import api as a
+    return a
+
+
+def blocks(n, seed, ks=(3, 4, 5), count=6, ctrl=True):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        k = ks[i % len(ks)]
+        nc = int(rng.integers(0, 6 - k)) if ctrl else 0
+        q = rng.permutation(n)[: k + nc]
+        out.append(qsynth.gate("MAT", q[:k], q[k:], mat=qsynth.haar_unitary(1 << k, rng)))
+        # interleave ordinary gates so tiled and MFMA passes alternate
+        out.append(qsynth.gate("H", (int(rng.integers(0, n)),)))
+        out.append(qsynth.gate("U1", (int(q[0]),), (int((q[0] + 1) % n),), theta=0.7))
+    return out
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("n", [12, 15])
+def test_mfma_blocks_vs_oracle(api, dt, n):
+    banner("mfma", dt, n)
+    spec = blocks(n, 10 + n)
+    c = api.Circuit.from_spec(n, spec, use_mfma=1)
+    kinds = [k for k, _, _ in c.passes()]
+    assert kinds.count(4) >= 6, kinds
+    psi0 = qsynth.random_state(n, n)
+    st = gpu_state(api, n, dt, psi0)
+    c.run(st)
+    ref = ocirc.run(n, spec, oracle_input(psi0, dt))
+    assert maxabs(st.download(), ref) < TOL[dt]
+
+
+def test_mfma_low_and_high_targets(api):
+    n = 14
+    banner("mfma targets")
+    rng = np.random.default_rng(3)
+    spec = []
+    for tg in [(13, 12, 11, 10, 9), (0, 1, 2, 3, 4), (0, 13, 6, 7, 2), (5, 4, 3, 2)]:
+        spec.append(qsynth.gate("MAT", tg, mat=qsynth.haar_unitary(1 << len(tg), rng)))
+    psi0 = qsynth.random_state(n, 4)
+    for dt in ("c64", "c128"):
+        c = api.Circuit.from_spec(n, spec, use_mfma=1)
+        st = gpu_state(api, n, dt, psi0)
+        c.run(st)
+        assert maxabs(st.download(), ocirc.run(n, spec, oracle_input(psi0, dt))) < TOL[dt]
+
+
+def test_mfma_adjoint_passes(api):
+    # an energy gradient through a circuit with matrix-core blocks
+    from oracle import gradients as ograd
+    n = 12
+    banner("mfma adjoint")
+    rng = np.random.default_rng(5)
+    spec = [qsynth.gate("RY", (q,), pidx=q) for q in range(n)]
+    spec.append(qsynth.gate("MAT", (2, 5, 7, 9), mat=qsynth.haar_unitary(16, rng)))
+    spec += [qsynth.gate("RX", (q,), pidx=n + q) for q in range(n)]
+    params = rng.uniform(0, 2 * np.pi, 2 * n)
+    terms = qsynth.random_pauli_sum(n, 8, 2)
+    c = api.Circuit.from_spec(n, spec, use_mfma=1)
+    assert 4 in [k for k, _, _ in c.passes()]
+    psi, lam = api.State(n, "c128"), api.State(n, "c128")
+    c.run(psi, params)
+    H = api.Observable.pauli_sum(n, terms)
+    e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+    e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+    assert abs(e - e_ref) < 1e-10 and np.max(np.abs(g - g_ref)) < 1e-10
+
+
+@pytest.mark.parametrize("fuse_k", [2, 3, 4, 5])
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_fused_circuits_vs_oracle(api, dt, fuse_k):
+    # gate fusion (the paper's fuse step, widened to k qubits) must leave the
+    # final state unchanged: random layers with controls, and the QFT
+    n = 14
+    banner("fuse", dt, fuse_k)
+    psi0 = qsynth.random_state(n, 30 + fuse_k)
+    for spec in (qsynth.random_mixed(n, 90, 40 + fuse_k), qsynth.qft(n)):
+        c = api.Circuit.from_spec(n, spec, fuse_k=fuse_k)
+        st = gpu_state(api, n, dt, psi0)
+        c.run(st)
+        ref = ocirc.run(n, spec, oracle_input(psi0, dt))
+        assert maxabs(st.download(), ref) < TOL[dt] * 4
+
+
+def test_fused_variational_gradient(api):
+    # rotations keep their parameters through fusion; the gradient is unchanged
+    from oracle import gradients as ograd
+    n = 10
+    banner("fuse adjoint")
+    n, spec, params, terms = qsynth.variational_10q(2)
+    c = api.Circuit.from_spec(n, spec, fuse_k=4)
+    psi, lam = api.State(n, "c128"), api.State(n, "c128")
+    c.run(psi, params)
+    H = api.Observable.pauli_sum(n, terms)
+    e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+    e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+    assert abs(e - e_ref) < 1e-10 and np.max(np.abs(g - g_ref)) < 1e-10
+
+
+def test_autotune_keeps_results_and_caches(api, tmp_path):
+    n = 16
+    banner("autotune")
+    spec = qsynth.random_mixed(n, 120, 77, max_k=3)
+    cache = str(tmp_path / "tune.txt")
+    for dt in ("c64", "c128"):
+        c = api.Circuit.from_spec(n, spec)
+        st = api.State(n, dt)
+        api.autotune(c.h, st.h, None, cache)
+        lines = open(cache).read().splitlines()
+        assert lines and ("dtype=" + dt) in lines[-1]
+        api.autotune(c.h, st.h, None, cache)           # a cache hit appends nothing
+        assert open(cache).read().splitlines() == lines
+        psi0 = qsynth.random_state(n, 9)
+        st.upload(psi0.astype(np.complex64 if dt == "c64" else np.complex128))
+        c.run(st)
+        assert maxabs(st.download(), ocirc.run(n, spec, oracle_input(psi0, dt))) < TOL[dt] * 4
