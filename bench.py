@@ -2,25 +2,32 @@
 """Benchmark of the state-vector hot path on one MI355X.
 
 One step = one pass of the whole 30-qubit hot path on seeded synthetic input,
-complex64 amplitudes with float64 accumulation:
-  1. QFT on 30 qubits (H, controlled phase, SWAP: 480 gates) on a random state;
-  2. a 30-qubit variational circuit (10 layers of RY on every qubit + CZ ring,
-     600 gates, 300 angles ~ U[0, 2pi)) from |0..0>;
-  3. its energy <H>, H = sum Z_i Z_{i+1} (ring) + 0.5 sum X_i;
-  4. the adjoint gradient of that energy (all 300 angles);
-  5. 100000 measurement shots of the QFT output (all qubits).
-value = forward gates (480 + 600) per second of the whole step.
+complex64 amplitudes (float32 pairs) with float64 accumulation:
+  1. QFT on 30 qubits (H, controlled phase, SWAP: 480 gates) on a random
+     normalised state (re, im ~ N(0,1));
+  2. 100000 measurement shots of all 30 qubits of the QFT output;
+  3. six dense k-qubit blocks (k = 5, 5, 5, 4, 4, 4 on low, high and mixed
+     qubits, Haar matrices) on the same state, on matrix cores;
+  4. a 30-qubit variational circuit (10 layers of RY on every qubit + CZ
+     ring: 600 gates, 300 angles ~ U[0, 2pi)) from |0..0>;
+  5. its energy <H>, H = sum Z_i Z_{i+1} (ring) + 0.5 sum X_i;
+  6. the adjoint gradient of that energy (all 300 angles);
+  7. 10 second-order Trotter steps of adiabatic evolution (H0 = -sum X,
+     H1 = random 30-qubit Ising, dt = 0.01) from |+..+>.
+value = user-level forward gates of the step (480 + 6 + 600 + 10 * 61) per
+second of the whole step (energy, gradient and shots included in the time).
 
-Prints ONE JSON line.  Also measured in the same run (outside the timed
-steps) and reported in the line: adjoint/forward time ratio, QFT-only gates/s,
-the 24-qubit complex128 adiabatic run (1000 Trotter steps) and the batched
-variational workload.
+Prints ONE JSON line.  Outside the timed steps the same run measures, and
+reports in the line: the batched workload (512 uneven variational instances,
+graph replay) and the 24-qubit complex128 adiabatic run (1000 steps).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -28,24 +35,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 METRIC = "state-vector GB/s & gates/s at 30 qubits; adjoint-grad / forward time ratio"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile2_f32_30q_step_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2009_01845_amd", "csrc", "kernels.hip")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n: int):
-    """The CPU oracle on a bounded sample of the same workload: the first two
-    QFT-30 gates (H, controlled phase) on a basis state, complex128."""
-    import numpy as np
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per tiled-pass launch from the committed counter summary, or
+    None when it is missing or was taken on another version of the kernels."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    src = re.search(r"kernels_sha256_16:\s*([0-9a-f]+)", text)
+    val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not src or not val or src.group(1) != kernel_source_hash():
+        return None
+    return float(val.group(1))
+
+
+def cpu_baseline(n: int, budget_s: float = 12.0):
+    """The CPU oracle on a bounded sample of the same workload: QFT-n gates in
+    order on a basis state (numpy, complex128) until the time budget is used."""
     import qsynth
     from oracle import gates as og, statevec as sv
-    spec = qsynth.qft(n)[:2]
+    spec = qsynth.qft(n)
     psi = sv.basis(n, 12345)
+    done = 0
     t = time.perf_counter()
     for g in spec:
         psi = sv.apply(psi, og.gate_matrix(g), g.targets, g.controls)
+        done += 1
+        if time.perf_counter() - t > budget_s:
+            break
     dt = time.perf_counter() - t
     try:
         import threadpoolctl
@@ -53,9 +85,20 @@ def cpu_baseline(n: int):
     except Exception:  # pragma: no cover
         thr = 1
     del psi
-    return {"value": len(spec) / dt, "unit": "gates/s", "cores": int(thr), "kind": "oracle",
-            "sample": f"first {len(spec)} QFT-{n} gates on a basis state, numpy complex128, {dt:.1f} s; "
+    return {"value": done / dt, "unit": "gates/s", "cores": int(thr), "kind": "oracle",
+            "sample": f"first {done} of the {len(spec)} QFT-{n} gates on a basis state, numpy complex128, "
+                      f"{dt:.1f} s (elementwise numpy work runs on one thread; BLAS pool {thr}); "
                       f"host has {os.cpu_count()} logical CPUs"}
+
+
+def dense_blocks(n: int, seed: int = 11):
+    """k = 5, 5, 5, 4, 4, 4 Haar blocks on the low, high and spread qubits."""
+    import numpy as np
+    import qsynth
+    rng = np.random.default_rng(seed)
+    sets = [tuple(range(n - 5, n)), tuple(range(5)), (0, n // 4, n // 2, 3 * n // 4, n - 1),
+            tuple(range(n - 4, n)), tuple(range(4)), (3, n // 3 + 1, 2 * n // 3, n - 3)]
+    return [qsynth.gate("MAT", t, mat=qsynth.haar_unitary(1 << len(t), rng)) for t in sets]
 
 
 def main():
@@ -65,11 +108,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--shots", type=int, default=100000)
+    ap.add_argument("--trotter-steps", type=int, default=10)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        sys.exit("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)")
+        sys.exit("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)")
 
     import numpy as np
     import torch
@@ -90,36 +135,52 @@ def main():
     psi_in /= torch.linalg.vector_norm(psi_in)
     del v
     qft = api.Circuit.from_spec(n, qsynth.qft(n))
-    vn, vspec, vparams, vterms = qsynth.gradient_20q(seed=0, n=n, layers=10)
+    blocks = api.Circuit.from_spec(n, dense_blocks(n), use_mfma=1)
+    _, vspec, vparams, vterms = qsynth.gradient_20q(seed=0, n=n, layers=10)
     var = api.Circuit.from_spec(n, vspec)
     H = api.Observable.pauli_sum(n, vterms)
+    J, hz = qsynth.ising_couplings(n, 1)
+    ising = api.Observable.ising(n, J, hz)
+    tro_T, tro_dt = args.trotter_steps * 0.01, 0.01
     st_q = api.State(n, "c64")
     st_v = api.State(n, "c64")
     lam = api.State(n, "c64")
-    qft_gates = qft.info()[0]
-    var_gates = var.info()[0]
-    log("n", n, "qft passes", qft.info()[1], "var passes", var.info()[1])
+    if not args.no_autotune:
+        t = time.perf_counter()
+        qft.autotune(st_q)
+        var.autotune(st_v, vparams)
+        log(f"autotune {time.perf_counter() - t:.1f} s")
+    qft_gates, var_gates, blk_gates = qft.info()[0], var.info()[0], blocks.info()[0]
+    tro_gates = args.trotter_steps * (2 * n + 1)
+    fwd_gates = qft_gates + blk_gates + var_gates + tro_gates
+    log("n", n, "passes: qft", qft.info()[1], "blocks", blocks.info()[1], "var", var.info()[1])
 
-    comp = {"qft": 0.0, "var_fwd": 0.0, "energy": 0.0, "adjoint": 0.0, "sample": 0.0}
+    names = ["qft", "sample", "blocks", "var_fwd", "energy", "adjoint", "trotter"]
+    comp = {k: 0.0 for k in names}
 
     def step(timed: bool):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
         ev[0].record(stream)
         st_q.tensor.copy_(psi_in)
         qft.run(st_q)
         ev[1].record(stream)
+        api.sample(st_q.h, list(range(n)), args.shots, seed=7)
+        ev[2].record(stream)
+        blocks.run(st_q)
+        ev[3].record(stream)
         st_v.set_basis(0)
         var.run(st_v, vparams)
-        ev[2].record(stream)
-        H.expectation(st_v)
-        ev[3].record(stream)
-        api.adjoint(var.h, vparams, H.h, st_v.h, lam.h, var.nparams)
         ev[4].record(stream)
-        api.sample(st_q.h, list(range(n)), args.shots, seed=7)
+        H.expectation(st_v)
         ev[5].record(stream)
+        api.adjoint(var.h, vparams, H.h, st_v.h, lam.h, var.nparams)
+        ev[6].record(stream)
+        st_v.set_plus()
+        api.adiabatic_run(st_v.h, ising.h, tro_T, tro_dt)
+        ev[7].record(stream)
         if timed:
             torch.cuda.synchronize()
-            for k, (a, b) in zip(comp, zip(ev[:-1], ev[1:])):
+            for k, a, b in zip(names, ev[:-1], ev[1:]):
                 comp[k] += a.elapsed_time(b)
 
     for _ in range(args.warmup):
@@ -135,20 +196,24 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     api.profile_enable(False)
-    tile_n, tile_ms = api.profile_read(0)
-    perm_n, perm_ms = api.profile_read(2)
-    adj_n, adj_ms = api.profile_read(7)
+    fam = {f: api.profile_read(i) for i, f in enumerate(
+        ["tile", "phase", "perm", "mfma", "dense", "reduce", "sample", "adjoint", "batch", "other"])}
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = (qft_gates + var_gates) / (ms_per_step / 1e3)
+    value = fwd_gates / (ms_per_step / 1e3)
 
     bytes_pass = 2 * (1 << n) * 8  # one read + one write of every complex64 amplitude
+    tile_n, tile_ms = fam["tile"]
     tile_avg = tile_ms / max(tile_n, 1)
     achieved = bytes_pass / (tile_avg / 1e3) / 1e9
+    traffic = load_traffic()
     per = {k: v / args.steps for k, v in comp.items()}
     fwd_ms = per["var_fwd"] + per["energy"]
-    qft_gps = qft_gates / (per["qft"] / 1e3)
+    mf_n, mf_ms = fam["mfma"]
+    # the six blocks: 3 of k = 5 and 3 of k = 4, 8 * 2^k * 2^n real flops each
+    mf_flops = 3 * 8 * 32 * (1 << n) + 3 * 8 * 16 * (1 << n)
+    mf_tflops = mf_flops / (mf_ms / max(mf_n, 1) * 6 / 1e3) / 1e12 if mf_n else None
+    mf_gbs = bytes_pass / (mf_ms / max(mf_n, 1) / 1e3) / 1e9 if mf_n else None
     passes_total = qft.info()[1] + var.info()[1]
-    gbps_state = passes_total * bytes_pass / ((per["qft"] + per["var_fwd"]) / 1e3) / 1e9
 
     out = {
         "metric": METRIC,
@@ -161,39 +226,66 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (fp32 pairs, fp64 accumulation)",
+        "dtype": "f32",
         "data": "synthetic (seeded)",
-        "config": {"workload": f"QFT-{n} + variational-{n} energy and adjoint gradient + {args.shots} shots",
-                   "n_qubits": n, "qft_gates": qft_gates, "variational_gates": var_gates,
-                   "variational_params": var.nparams, "shots": args.shots, "parallelism": "single GPU"},
-        "gbps_state_passes": gbps_state,
-        "qft_gates_per_s": qft_gps,
+        "config": {"workload": f"{n}-qubit hot path: QFT-{n} + {args.shots} shots + 6 dense k=4/5 blocks + "
+                               f"variational-{n} energy and adjoint gradient + {args.trotter_steps} Trotter steps",
+                   "n_qubits": n, "amplitudes": "complex64, float64 accumulation",
+                   "qft_gates": qft_gates, "dense_blocks": blk_gates, "variational_gates": var_gates,
+                   "variational_params": var.nparams, "trotter_steps": args.trotter_steps,
+                   "trotter_gates": tro_gates, "shots": args.shots, "forward_gates_per_step": fwd_gates},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_tile2<float> (register-staged tiled pass)", "launches": tile_n,
+                     "avg_launch_ms": tile_avg, "algorithmic_bytes_per_launch": bytes_pass},
+        "qft_gates_per_s": qft_gates / (per["qft"] / 1e3),
+        "state_gbps_qft_and_variational": passes_total * bytes_pass / ((per["qft"] + per["var_fwd"]) / 1e3) / 1e9,
         "adjoint_over_forward": per["adjoint"] / fwd_ms,
+        "mfma_blocks": {"tflops": mf_tflops, "peak_tflops": FP32_PEAK_TFLOPS,
+                        "util": mf_tflops / FP32_PEAK_TFLOPS if mf_tflops else None,
+                        "hbm_gbps": mf_gbs, "launches": mf_n},
         "components_ms": per,
-        "roofline": {"bound": "hbm", "kernel": "k_tile<float> (tiled pass)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "launches": tile_n, "avg_launch_ms": tile_avg,
-                     "algorithmic_bytes_per_launch": bytes_pass},
-        "perm_pass_avg_ms": perm_ms / max(perm_n, 1),
-        "adjoint_pass_avg_ms": adj_ms / max(adj_n, 1),
+        "family_avg_ms": {k: (ms / c if c else None) for k, (c, ms) in fam.items()},
+        "kernels_sha256_16": kernel_source_hash(),
     }
     del st_q, st_v, lam, psi_in
     torch.cuda.empty_cache()
 
     if not args.no_extras:
         ex = {}
+        # batched uneven instances, one persistent launch replayed as a graph
+        insts = qsynth.batch_instances(seed=0)
+        circs = [api.Circuit.from_spec(m, spec) for m, spec, _, _ in insts]
+        obs = [api.Observable.pauli_sum(m, terms) for m, _, _, terms in insts]
+        bparams = np.concatenate([p for _, _, p, _ in insts])
+        b = api.Batch(circs, obs, "c64")
+        b.run(bparams)
+        b.run(bparams)
+        reps = 5
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            b.run(bparams)
+        dtb = (time.perf_counter() - t) / reps
+        bg = sum(c.info()[0] for c in circs)
+        ex["batch512_ms_per_replay"] = dtb * 1e3
+        ex["batch512_instances_per_s"] = len(insts) / dtb
+        ex["batch512_forward_gates_per_s"] = bg / dtb
+        ex["batch512_gates"] = bg
+        del b, circs, obs
+        log("batch done")
         # adiabatic evolution, 24 qubits complex128, T = 10, dt = 0.01
-        na, J, h, T, dta = qsynth.adiabatic_24q(0)
+        na, Ja, ha, T, dta = qsynth.adiabatic_24q(0)
         st = api.State(na, "c128")
         st.set_plus()
-        I = api.Observable.ising(na, J, h)
+        I = api.Observable.ising(na, Ja, ha)
         torch.cuda.synchronize()
         t = time.perf_counter()
         e = api.adiabatic_run(st.h, I.h, T, dta)
         ex["adiabatic_24q_c128_s"] = time.perf_counter() - t
         ex["adiabatic_24q_energy"] = e
         ex["adiabatic_24q_overlap_ground"] = float(
-            st.tensor[int(np.argmin(_ising_e_gpu(J, h, na)))].abs().item() ** 2)
+            st.tensor[int(np.argmin(_ising_e_gpu(Ja, ha, na)))].abs().item() ** 2)
         del st
         log("adiabatic done")
         out["extras"] = ex

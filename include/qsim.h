@@ -208,7 +208,7 @@ qs_status qs_batch_run(qs_batch* b, const double* params_packed, double* energie
 qs_status qs_batch_destroy(qs_batch* b);
 
 /* ------------------------------------------------------------------- tuner
- * Time the candidate plans (tile width, fusion width, MFMA on/off) of c on
+ * Time the candidate plans (fusion width 0, 2..5, MFMA on/off) of c on
  * state s, keep the fastest whose result from |+...+> agrees with the
  * default plan's (2-norm distance below 1e-4 for complex64, 1e-9 for
  * complex128), and compile c with it.  cache_path (may be NULL) is a text

@@ -92,6 +92,12 @@ hipError_t launch_sumsq(bool dbl, const void* psi, int n, double* partials, hipS
 hipError_t launch_dot_re(bool dbl, const void* a, const void* b, int n, double* partials, hipStream_t s);
 hipError_t launch_expect_group(bool dbl, const void* psi, int n, uint64_t flip, const PauliTermDev* terms,
                                int nterms, double* partials, hipStream_t s);
+// One partial per workgroup of sum_x |psi_x|^2 E(x) for a diagonal observable
+// written as a quadratic polynomial in the index bits: poly = [c, mu[n],
+// lam[n*n] (upper triangle used)]; elo[j] (j < 2^min(n,12)) = the terms of
+// the low 12 bits alone, without c.
+hipError_t launch_expect_poly(bool dbl, const void* psi, int n, const double* poly, const double* elo,
+                              double* partials, hipStream_t s);
 // lambda = sum_g sum_t c_t P_t psi over all groups (adjoint seed H psi)
 hipError_t launch_apply_hamiltonian(bool dbl, const void* psi, void* lam, int n, const uint64_t* flips,
                                     const int* group_off, int ngroups, const PauliTermDev* terms,

@@ -587,6 +587,74 @@ __global__ __launch_bounds__(256) void k_expect(const typename CT<R>::C* __restr
   if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
+// Diagonal observable given as a quadratic polynomial in the index bits,
+// E(x) = c + sum_p mu_p x_p + sum_{p<q} lam_pq x_p x_q  (poly = [c, mu[n], lam[n*n]]).
+// Rows of 2^12 amplitudes (the low 12 bits j, the high bits h fixed):
+//   E = A(h) + Elo[j] + N1[j & 63] + N2[j >> 6],
+// Elo the pass-constant table of the low-bit terms, A the high-bit terms and
+// N1/N2 the cross terms nu_p(h) = sum_{q high, x_q = 1} lam_pq summed over
+// the set bits of each half of j.  Partials of sum |psi|^2 E per workgroup.
+template <typename R>
+__global__ __launch_bounds__(256) void k_expect_poly(const typename CT<R>::C* __restrict__ psi, int n,
+                                                     const double* __restrict__ poly, const double* __restrict__ elo,
+                                                     double* __restrict__ part) {
+  constexpr int LB = 12;
+  __shared__ double sElo[1 << LB];
+  __shared__ double nu[LB];
+  __shared__ double N1[64], N2[64];
+  __shared__ double sA;
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  const int lb = n < LB ? n : LB;
+  const int rows = 1 << lb;
+  const int64_t ntiles = 1ll << (n - lb);
+  for (int j = tid; j < rows; j += blockDim.x) sElo[j] = elo[j];
+  const double* mu = poly + 1;
+  const double* lam = poly + 1 + n;
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t hbits = (uint64_t)t << lb;  // the row's high index bits
+    __syncthreads();                            // the previous row is done with nu, N1, N2, sA
+    if (tid < 64) {
+      // lane q < n - lb: the terms whose lowest set high bit is q; lanes 32..: nu
+      double a = 0.0;
+      const int q = lb + tid;
+      if (tid < 32 && q < n && ((hbits >> q) & 1)) {
+        a = mu[q];
+        for (int r = q + 1; r < n; ++r)
+          if ((hbits >> r) & 1) a += lam[q * n + r];
+      }
+      for (int off = 16; off > 0; off >>= 1) a += __shfl_xor(a, off, 32);
+      if (tid == 0) sA = poly[0] + a;
+      if (tid >= 32 && tid - 32 < lb) {
+        const int pb = tid - 32;
+        double v = 0.0;
+        for (int r = lb; r < n; ++r)
+          if ((hbits >> r) & 1) v += lam[pb * n + r];
+        nu[pb] = v;
+      }
+    }
+    __syncthreads();
+    if (tid < 128) {
+      const int half = tid >> 6, a = tid & 63;
+      double v = 0.0;
+      for (int b = 0; b < 6; ++b)
+        if (((a >> b) & 1) && 6 * half + b < lb) v += nu[6 * half + b];
+      if (half) N2[a] = v;
+      else N1[a] = v;
+    }
+    __syncthreads();
+    const double A = sA;
+    for (int j = tid; j < rows; j += blockDim.x) {
+      const auto v = psi[hbits | (uint64_t)j];
+      const double e = A + sElo[j] + N1[j & 63] + N2[j >> 6];
+      acc += ((double)v.x * v.x + (double)v.y * v.y) * e;
+    }
+  }
+  const double r = block_sum(acc, red);
+  if (tid == 0) part[blockIdx.x] = r;
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_apply_ham(const typename CT<R>::C* __restrict__ psi,
                                                    typename CT<R>::C* __restrict__ lam, int n,
@@ -932,12 +1000,15 @@ struct PassSmem {
   double phCk[kMaxPhasePerPass][kMaxKBits];
   int hb[kMaxTileBits];
   int kpos[kMaxKBits];
+  double gacc[kMaxGradPerPass][kThreads / 64];  // adjoint partials of this pass, per wave
 };
 
 // One staged pass over tiles t_first, t_first + t_step, ... < ntiles; the
 // tile-index bits above gbits are the "k bits" of the phase tables.  GUARD:
 // tiles may be smaller than one full sweep of the workgroup.  Gradient
-// partials go to gpart[gslot * gstride + gcol + wave].
+// partials are summed in LDS over the workgroup's tiles and stored once, at
+// gpart[gslot * gstride + gcol + wave] (each op owns its slot, so every entry
+// has exactly one writer).
 template <typename R, bool TWO, int NLD, bool GUARD>
 __device__ __forceinline__ void pass_body(
     typename CT<R>::C* __restrict__ psi, typename CT<R>::C* __restrict__ lam, const PassGeom& g,
@@ -967,6 +1038,8 @@ __device__ __forceinline__ void pass_body(
   const int nph = g.nph, ph0 = g.ph0, nst = g.nst, st0 = g.st0, op0 = g.op0;
   const int kb = (n - m) - gbits;
   if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
+  if (TWO)
+    for (int i = tid; i < kMaxGradPerPass * (kThreads / 64); i += blockDim.x) (&sm.gacc[0][0])[i] = 0.0;
   if (tid == 0) {  // global positions of the tile-index bits above the grid
     int idx = 0;
     uint64_t tm = (1ull << L) - 1;
@@ -1095,7 +1168,7 @@ __device__ __forceinline__ void pass_body(
             if (TWO && kind == OP_ROT && ops[o].gslot >= 0) {
               double pg = act ? rgrad_any(v, w, k, creg, ops[o].pauli) : 0.0;
               for (int off = 32; off > 0; off >>= 1) pg += __shfl_xor(pg, off, 64);
-              if ((tid & 63) == 0) gpart[(int64_t)ops[o].gslot * gstride + gcol + (tid >> 6)] += pg;
+              if ((tid & 63) == 0) sm.gacc[ops[o].aux][tid >> 6] += pg;
             }
             if (!act) continue;
             const C* mp = matc + ops[o].mat + (TWO ? 4 : 0);
@@ -1153,13 +1226,9 @@ __device__ __forceinline__ void pass_body(
             const C F2 = expi<C>(phNu[p][st.rb[2]] + scl * bt[3]);
             const C F3 = expi<C>(phNu[p][st.rb[3]] + scl * bt[4]);
             const C* qt = qtab + rec.wr_off;
-            // factor of register element e = exp(i th) * prod_{k in e} F_k (* wr[e]):
-            // a product tree over the four register bits, written out
-            const C f0 = expi<C>(th), f1 = cmul(f0, F0);
-            const C f2 = cmul(f0, F1), f3 = cmul(f1, F1);
-            const C f4 = cmul(f0, F2), f5 = cmul(f1, F2), f6 = cmul(f2, F2), f7 = cmul(f3, F2);
-            const C f8 = cmul(f0, F3), f9 = cmul(f1, F3), f10 = cmul(f2, F3), f11 = cmul(f3, F3);
-            const C f12 = cmul(f4, F3), f13 = cmul(f5, F3), f14 = cmul(f6, F3), f15 = cmul(f7, F3);
+            // factor of register element e = exp(i th) * prod_{k in e} F_k (* wr[e]),
+            // visited in Gray-code order with one running factor: each step
+            // sets a bit (times F_k) or clears one (times conj F_k, |F_k| = 1)
             const bool wtriv = rec.wr_trivial != 0;
             const bool wscaled = rec.scale_idx >= 0;
             auto apply = [&](int e, C fe) {
@@ -1172,10 +1241,23 @@ __device__ __forceinline__ void pass_body(
               v[e] = cmul(v[e], fe);
               if (TWO) w[e] = cmul(w[e], fe);
             };
-            apply(0, f0); apply(1, f1); apply(2, f2); apply(3, f3);
-            apply(4, f4); apply(5, f5); apply(6, f6); apply(7, f7);
-            apply(8, f8); apply(9, f9); apply(10, f10); apply(11, f11);
-            apply(12, f12); apply(13, f13); apply(14, f14); apply(15, f15);
+            C f = expi<C>(th);
+            apply(0, f);
+            f = cmul(f, F0); apply(1, f);
+            f = cmul(f, F1); apply(3, f);
+            f = cmul(f, cconj(F0)); apply(2, f);
+            f = cmul(f, F2); apply(6, f);
+            f = cmul(f, F0); apply(7, f);
+            f = cmul(f, cconj(F1)); apply(5, f);
+            f = cmul(f, cconj(F0)); apply(4, f);
+            f = cmul(f, F3); apply(12, f);
+            f = cmul(f, F0); apply(13, f);
+            f = cmul(f, F1); apply(15, f);
+            f = cmul(f, cconj(F0)); apply(14, f);
+            f = cmul(f, cconj(F2)); apply(10, f);
+            f = cmul(f, F0); apply(11, f);
+            f = cmul(f, cconj(F1)); apply(9, f);
+            f = cmul(f, cconj(F0)); apply(8, f);
           }
         }
         if (valid) {
@@ -1202,6 +1284,14 @@ __device__ __forceinline__ void pass_body(
         if (!GUARD || (u * (int)blockDim.x + tid) * VW < M) *reinterpret_cast<VT*>(dstg + gaddr(base, u)) = buf[u];
     }
     __syncthreads();
+  }
+  if (TWO) {  // the partials are complete after the last barrier above
+    for (int i = tid; i < g.nops * (kThreads / 64); i += blockDim.x) {
+      const int oi = i / (kThreads / 64), w = i % (kThreads / 64);
+      const TileOp& op = ops[op0 + oi];
+      if (op.kind == OP_ROT && op.gslot >= 0) gpart[(int64_t)op.gslot * gstride + gcol + w] = sm.gacc[op.aux][w];
+    }
+    __syncthreads();  // a following pass in the same workgroup reuses gacc
   }
 }
 
@@ -1740,6 +1830,21 @@ hipError_t launch_expect_group(bool dbl, const void* psi, int n, uint64_t flip, 
                        nterms, partials);
   else
     hipLaunchKernelGGL((k_expect<float>), dim3(grid), dim3(256), 0, s, (const float2*)psi, n, flip, terms, nterms,
+                       partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_expect_poly(bool dbl, const void* psi, int n, const double* poly, const double* elo,
+                              double* partials, hipStream_t s) {
+  if (n < 1 || n > kMaxQubits) return hipErrorInvalidValue;
+  const int lb = n < 12 ? n : 12;
+  const int64_t nt = 1ll << (n - lb);
+  const int grid = (int)(nt < kGridMax ? nt : kGridMax);
+  if (dbl)
+    hipLaunchKernelGGL((k_expect_poly<double>), dim3(grid), dim3(256), 0, s, (const double2*)psi, n, poly, elo,
+                       partials);
+  else
+    hipLaunchKernelGGL((k_expect_poly<float>), dim3(grid), dim3(256), 0, s, (const float2*)psi, n, poly, elo,
                        partials);
   return hipGetLastError();
 }

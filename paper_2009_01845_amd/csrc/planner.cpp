@@ -348,6 +348,12 @@ int nphase_raw(const std::vector<RawOp>& raw) {
   return c;
 }
 
+int ngrad_raw(const std::vector<RawOp>& raw) {
+  int c = 0;
+  for (const RawOp& r : raw) c += r.kind == OP_ROT && r.g.pidx >= 0;
+  return c;
+}
+
 bool has(const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); }
 
 // Register-blocked form of a pass (tiles of >= 2^12 amplitudes): split its op
@@ -576,6 +582,7 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
   for (int b = 0; b < L; ++b) pos[b] = b;
   for (int j = 0; j < g.H; ++j) pos[L + j] = g.hbits[j];
 
+  int ngrad = 0;
   for (RawOp& r : raw) {
     TileOp op;
     std::memset(&op, 0, sizeof(op));
@@ -602,7 +609,11 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
       if (r.kind == OP_ROT) {
         op.pidx = bg.pidx;
         op.pauli = bg.pauli == 'X' ? 1 : bg.pauli == 'Y' ? 2 : 3;
-        if (bg.pidx >= 0) op.gslot = plan.ngrad_slots++;
+        if (bg.pidx >= 0) {
+          if (ngrad >= kMaxGradPerPass) throw std::runtime_error("planner: too many parameters in one pass");
+          op.gslot = plan.ngrad_slots++;
+          op.aux = ngrad++;
+        }
         op.mat = (int)plan.matpool.size();  // forward and inverse 2x2, written per run
         plan.matpool.insert(plan.matpool.end(), 8, cd(0, 0));
       } else {
@@ -903,6 +914,10 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
           continue;
         }
         if (b.nmask && nphase_raw(raw) >= kMaxPhasePerPass - 2) {  // keep the pass staged
+          ++it;
+          continue;
+        }
+        if (b.kind == BK_ROT && b.pidx >= 0 && ngrad_raw(raw) >= kMaxGradPerPass) {
           ++it;
           continue;
         }

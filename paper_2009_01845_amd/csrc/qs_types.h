@@ -36,7 +36,8 @@ struct TileOp {
   int32_t pidx;      // OP_ROT: parameter index
   int32_t pauli;     // OP_ROT: 1 = X, 2 = Y, 3 = Z
   int32_t sign;      // OP_ROT: +1 forward, -1 inverse
-  int32_t aux;       // OP_PHASE: phase record index; OP_DIAG: offset into diag pool
+  int32_t aux;       // OP_PHASE: phase record index; OP_DIAG: offset into diag pool;
+                     // OP_ROT with a gradient slot: its index among the pass's gradient ops
   int32_t gslot;     // adjoint: gradient slot of this op (-1 if none)
   uint32_t creg;     // staged passes: control mask over register slots
   uint32_t flags;    // bit 0: the matrix is real; bit 1 (OP_PHASE): every term holds register slot b[0]
@@ -44,6 +45,7 @@ struct TileOp {
 
 constexpr int kRegBits = 4;            // register slots per thread in a staged pass
 constexpr int kMaxPhasePerPass = 16;   // phase ops whose tile terms are prepared per tile
+constexpr int kMaxGradPerPass = 64;    // parameterised rotations per pass (adjoint partials kept in LDS)
 constexpr int kGridBits = 11;          // streaming grids hold at most 2^kGridBits workgroups
 constexpr int kMaxKBits = 12;          // tile-index bits above the grid: n - m - kGridBits <= 12
 

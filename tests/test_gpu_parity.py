@@ -174,6 +174,27 @@ def test_expectation_and_norm(api, dt):
     assert abs(I.expectation(st) - float(np.sum(np.abs(ref) ** 2 * oobs.ising_energies(J, h)))) < tol * 10
 
 
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("n", [5, 15, 20])
+def test_diagonal_polynomial_expectation(api, dt, n):
+    # diagonal groups with at most two Z factors per term take the polynomial
+    # path (rows of 2^12 amplitudes, high-bit and cross terms per row); a
+    # group with a three-Z term takes the generic term loop
+    banner("diagonal expectation", dt, n)
+    psi0 = qsynth.random_state(n, 300 + n)
+    st = gpu_state(api, n, dt, psi0)
+    ref = oracle_input(psi0, dt)
+    tol = 1e-11 if dt == "c128" else 2e-6
+    J, h = qsynth.ising_couplings(n, n)
+    I = api.Observable.ising(n, J, h)
+    e_ref = float(np.sum(np.abs(ref) ** 2 * oobs.ising_energies(J, h)))
+    assert abs(I.expectation(st) - e_ref) < tol * max(1.0, abs(e_ref))
+    for terms in (qsynth.zz_ring_plus_x(n),
+                  qsynth.zz_chain(n, periodic=False) + [(0.7, qsynth.pauli_string(n, {0: "Z", 1: "Z", n - 1: "Z"}))]):
+        H = api.Observable.pauli_sum(n, terms)
+        assert abs(H.expectation(st) - oobs.expectation(ref, terms).real) < tol * n
+
+
 # ---------------------------------------------------------------- sampling
 @pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("shots", [1, 7, 4099])
