@@ -109,7 +109,7 @@ def main():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--shots", type=int, default=100000)
     ap.add_argument("--trotter-steps", type=int, default=10)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="pick each 30-qubit circuit's plan by timing first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
@@ -145,7 +145,7 @@ def main():
     st_q = api.State(n, "c64")
     st_v = api.State(n, "c64")
     lam = api.State(n, "c64")
-    if not args.no_autotune:
+    if args.autotune:
         t = time.perf_counter()
         qft.autotune(st_q)
         var.autotune(st_v, vparams)

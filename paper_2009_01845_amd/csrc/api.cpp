@@ -135,9 +135,20 @@ void check_device() {
 }
 
 // Device copy of a plan.
+template <typename T> void upload_complex(DBuf& d, const std::vector<cd>& v, bool dbl, hipStream_t s) {
+  std::vector<T> f(v.size() * 2);
+  for (size_t i = 0; i < v.size(); ++i) {
+    f[2 * i] = (T)v[i].real();
+    f[2 * i + 1] = (T)v[i].imag();
+  }
+  upload(d, f, s);
+  (void)dbl;
+}
+
 struct DevPlanBuf {
-  DBuf ops, mat, dpool, phases, qtab, qang, stages, phlist, btab, matc;
+  DBuf ops, mat, dpool, phases, qtab, qang, stages, phlist, btab, matc, ctab;
   bool has_rot = false;
+  bool has_scaled = false;
   DevPlan view;
   bool dbl = false;
   std::vector<PassGeom> geoms;  // op0 filled in
@@ -173,6 +184,10 @@ struct DevPlanBuf {
     upload(phlist, p.phlist, s);
     upload(btab, p.btab, s);
     dbl = p.dbl;
+    if (dbl) upload_complex<double>(ctab, p.ctab, dbl, s);
+    else upload_complex<float>(ctab, p.ctab, dbl, s);
+    has_scaled = false;
+    for (const PhaseRec& r : p.phases) has_scaled |= r.scale_idx >= 0 && r.ctab_off >= 0;
     if (dbl) {
       std::vector<double> q(p.qtab.size() * 2);
       for (size_t i = 0; i < p.qtab.size(); ++i) {
@@ -198,6 +213,8 @@ struct DevPlanBuf {
     view.phlist = phlist.as<int32_t>();
     view.btab = btab.as<double>();
     view.matc = matc.p;
+    view.ctab = ctab.p;
+    view.nphases = (int)p.phases.size();
     view.nops_total = (int)all.size();
   }
 };
@@ -265,7 +282,7 @@ struct qs_batch {
   hipStream_t stream = nullptr;
   std::vector<BatchInst> insts;
   std::vector<PassGeom> geoms;
-  DBuf d_insts, d_order, d_geoms, d_ops, d_stages, d_matc, d_phases, d_phlist, d_dpool, d_btab, d_qtab, d_qang;
+  DBuf d_insts, d_order, d_geoms, d_ops, d_stages, d_matc, d_phases, d_phlist, d_dpool, d_btab, d_qtab, d_qang, d_ctab;
   DBuf d_terms, d_slot_pidx, d_states, d_counter, d_params, d_gpart, d_energies, d_grads;
   double* h_params = nullptr;
   double* h_energies = nullptr;
@@ -319,6 +336,7 @@ void run_passes(const DevPlanBuf& dp, const Plan& plan, bool dbl, void* psi, voi
                 const double* scales, double* gpart, hipStream_t s) {
   const int np = (int)plan.passes.size();
   if (dp.has_rot && params) hipck(launch_rot_mats(dbl, dp.view, params, s), "rotation matrices");
+  if (dp.has_scaled && scales) hipck(launch_phase_tabs(dbl, dp.view, scales, s), "phase factors");
   for (int k = 0; k < np; ++k) {
     const int i = lam ? np - 1 - k : k;
     const Pass& ps = plan.passes[i];
@@ -894,10 +912,17 @@ qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, i
     const int n = s->n;
     const bool dbl = s->dbl();
     PhasePoly E = ising_poly(n, h1->J.data(), h1->h.data());
-    Plan step = plan_rx_layer(n, dbl, TuneOpts{}, &E);
+    // blocks of S steps share passes (the last pass of a step carries the next
+    // step's rotations on its tile bits); then the remainder and the last layer
+    const int S = (int)std::min<int64_t>(K, 8);
+    const int64_t nblk = K / S, rem = K % S;
+    Plan block = plan_trotter(n, dbl, TuneOpts{}, &E, S);
+    Plan tail;
+    if (rem) tail = plan_trotter(n, dbl, TuneOpts{}, &E, (int)rem);
     Plan last = plan_rx_layer(n, dbl, TuneOpts{}, nullptr);
-    DevPlanBuf dstep, dlast;
-    dstep.load(step, s->stream);
+    DevPlanBuf dblock, dtail, dlast;
+    dblock.load(block, s->stream);
+    if (rem) dtail.load(tail, s->stream);
     dlast.load(last, s->stream);
     // merged RX angles and phase scales
     std::vector<double> ang(K + 1), scl(K);
@@ -912,9 +937,12 @@ qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, i
     DBuf dang, dscl;
     upload(dang, ang, s->stream);
     upload(dscl, scl, s->stream);
-    for (int64_t k = 0; k < K; ++k)
-      run_passes(dstep, step, dbl, s->ptr, nullptr, dang.as<double>() + k, dscl.as<double>() + k, nullptr,
+    for (int64_t b = 0; b < nblk; ++b)
+      run_passes(dblock, block, dbl, s->ptr, nullptr, dang.as<double>() + b * S, dscl.as<double>() + b * S, nullptr,
                  s->stream);
+    if (rem)
+      run_passes(dtail, tail, dbl, s->ptr, nullptr, dang.as<double>() + nblk * S, dscl.as<double>() + nblk * S,
+                 nullptr, s->stream);
     run_passes(dlast, last, dbl, s->ptr, nullptr, dang.as<double>() + K, nullptr, nullptr, s->stream);
     if (energy_out) {
       auto* o = const_cast<qs_obs*>(h1);
@@ -1013,7 +1041,7 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
     std::vector<PhaseRec> phases;
     std::vector<int32_t> phlist;
     std::vector<double> dpool, btab, qang;
-    std::vector<cd> qtab;
+    std::vector<cd> qtab, ctab;
     std::vector<PauliTermDev> terms;
     std::vector<int32_t> slot_pidx;
     std::vector<double> cost(count);
@@ -1044,6 +1072,9 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
       in.dp_base = (int)dpool.size();
       in.bt_base = (int)btab.size();
       in.qt_base = (int)qtab.size();
+      in.ct_base = (int)ctab.size();
+      for (const PhaseRec& r : p.phases)
+        if (r.scale_idx >= 0) fail(QS_E_UNSUPPORTED, "batch circuits cannot hold run-time scaled phases");
       int nops = 0;
       for (const Pass& ps : p.passes) {
         if (ps.kind != PASS_TILE || ps.geom.kern != 2)
@@ -1064,6 +1095,7 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
       btab.insert(btab.end(), p.btab.begin(), p.btab.end());
       qtab.insert(qtab.end(), p.qtab.begin(), p.qtab.end());
       qang.insert(qang.end(), p.qang.begin(), p.qang.end());
+      ctab.insert(ctab.end(), p.ctab.begin(), p.ctab.end());
       in.param_base = params;
       in.nparams = c->hc.nparams;
       params += c->hc.nparams;
@@ -1109,9 +1141,11 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
       if (b->dbl) {
         upload(b->d_matc, m, st);
         upload(b->d_qtab, q, st);
+        upload_complex<double>(b->d_ctab, ctab, true, st);
       } else {
         upload(b->d_matc, std::vector<float>(m.begin(), m.end()), st);
         upload(b->d_qtab, std::vector<float>(q.begin(), q.end()), st);
+        upload_complex<float>(b->d_ctab, ctab, false, st);
       }
     }
     const size_t esz = b->dbl ? 16 : 8;
@@ -1142,6 +1176,7 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
     a.dp.dpool = b->d_dpool.as<double>();
     a.dp.btab = b->d_btab.as<double>();
     a.dp.qtab = b->d_qtab.p;
+    a.dp.ctab = b->d_ctab.p;
     a.dp.qang = b->d_qang.as<double>();
     a.states = b->d_states.p;
     a.params = b->d_params.as<double>();
@@ -1327,8 +1362,7 @@ qs_status qs_autotune(qs_circuit* c, qs_state* s, const double* params, const ch
             "params upload");
       dpar = c->dparams.as<double>();
     }
-    std::vector<TuneChoice> cands = {{0, 0, -1, 0}, {0, 2, -1, 0}, {0, 3, 1, 0},
-                                     {0, 4, 0, 0},  {0, 4, 1, 0},  {0, 5, 1, 0}};
+    std::vector<TuneChoice> cands = {{0, 0, -1, 0}, {0, 2, -1, 0}, {0, 3, 1, 0}, {0, 4, 1, 0}, {0, 5, 1, 0}};
     DBuf ref;
     ref.ensure(s->bytes());
     double* part = scratch_doubles(s, kGridMax + 8);

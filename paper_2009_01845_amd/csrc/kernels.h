@@ -20,7 +20,9 @@ struct DevPlan {
   const int32_t* phlist = nullptr;
   const double* btab = nullptr;
   void* matc = nullptr;           // matrix pool in the state precision (rotation slots written per run)
+  void* ctab = nullptr;           // phase factors in the state precision (scaled records written per run)
   int nops_total = 0;
+  int nphases = 0;
 };
 
 constexpr int kGridMax = 2048;  // fixed upper bound on streaming grids (deterministic reductions)
@@ -46,7 +48,7 @@ struct PauliTermDev {
 struct BatchInst {
   int32_t n, npass, pass0, nops;
   int32_t ops_base, st_base, mat_base, ph_base;
-  int32_t phl_base, dp_base, bt_base, qt_base;
+  int32_t phl_base, dp_base, bt_base, qt_base, ct_base;
   int32_t param_base, nparams, slot_base, nslots;
   int32_t obs_off, obs_nterms, pad0, pad1;
   int64_t state_off, lam_off;  // elements of the batch state buffer
@@ -76,6 +78,8 @@ hipError_t launch_batch(bool dbl, const BatchArgs& a, hipStream_t s);
 
 // Fill the forward and inverse matrices of every rotation op from params.
 hipError_t launch_rot_mats(bool dbl, const DevPlan& dp, const double* params, hipStream_t s);
+// exp(i scale * angle) factors of every scaled phase record (scales[rec.scale_idx])
+hipError_t launch_phase_tabs(bool dbl, const DevPlan& dp, const double* scales, hipStream_t s);
 hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* tau, hipStream_t s);
 // Dense k-qubit block (k = 3..5) with matrix-core instructions; the tile is the
 // targets plus the 7 lowest other bits (g.m == k + 7); tl[t] = tile-local

@@ -6,6 +6,8 @@
 // the index arithmetic is 64-bit throughout (2^35 amplitudes).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 
@@ -846,6 +848,20 @@ constexpr int NR = kRegBits;
 constexpr int NE = 1 << kRegBits;
 
 
+// parity of a / pi for a phase angle that is a multiple of pi
+__device__ __forceinline__ bool pi_parity(double a) {
+  return (__double2ll_rn(a * 0.31830988618379067154) & 1ll) != 0;
+}
+// register elements whose slot-k bit is set
+__device__ __forceinline__ uint32_t slot_pattern(int k) {
+  return k == 0 ? 0xAAAAu : k == 1 ? 0xCCCCu : k == 2 ? 0xF0F0u : 0xFF00u;
+}
+template <typename C> __device__ __forceinline__ C cneg(C a) {
+  a.x = -a.x;
+  a.y = -a.y;
+  return a;
+}
+
 template <typename C> __device__ __forceinline__ C expi(double a);
 template <> __device__ __forceinline__ float2 expi<float2>(double a) {
   const double r = a - 6.283185307179586 * rint(a * 0.15915494309189535);
@@ -859,12 +875,12 @@ template <> __device__ __forceinline__ double2 expi<double2>(double a) {
   return make_double2(c, s);
 }
 
-template <int K, bool REAL, typename C>
+template <int K, bool REAL, bool CTRL, typename C>
 __device__ __forceinline__ void r1(C* v, C m00, C m01, C m10, C m11, uint32_t creg) {
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
     if (e & (1 << K)) continue;
-    if ((e & creg) != creg) continue;
+    if (CTRL && (e & creg) != creg) continue;
     const int f = e | (1 << K);
     const C a = v[e], b = v[f];
     if (REAL) {
@@ -881,20 +897,29 @@ __device__ __forceinline__ void r1(C* v, C m00, C m01, C m10, C m11, uint32_t cr
 
 template <bool REAL, typename C>
 __device__ __forceinline__ void r1_any(C* v, int k, C m00, C m01, C m10, C m11, uint32_t creg) {
+  if (creg == 0) {  // uniform: no register-slot controls
+    switch (k) {
+      case 0: r1<0, REAL, false>(v, m00, m01, m10, m11, 0); break;
+      case 1: r1<1, REAL, false>(v, m00, m01, m10, m11, 0); break;
+      case 2: r1<2, REAL, false>(v, m00, m01, m10, m11, 0); break;
+      default: r1<3, REAL, false>(v, m00, m01, m10, m11, 0); break;
+    }
+    return;
+  }
   switch (k) {
-    case 0: r1<0, REAL>(v, m00, m01, m10, m11, creg); break;
-    case 1: r1<1, REAL>(v, m00, m01, m10, m11, creg); break;
-    case 2: r1<2, REAL>(v, m00, m01, m10, m11, creg); break;
-    default: r1<3, REAL>(v, m00, m01, m10, m11, creg); break;
+    case 0: r1<0, REAL, true>(v, m00, m01, m10, m11, creg); break;
+    case 1: r1<1, REAL, true>(v, m00, m01, m10, m11, creg); break;
+    case 2: r1<2, REAL, true>(v, m00, m01, m10, m11, creg); break;
+    default: r1<3, REAL, true>(v, m00, m01, m10, m11, creg); break;
   }
 }
 
-template <int KH, int KL, typename C>
+template <int KH, int KL, bool CTRL, typename C>
 __device__ __forceinline__ void r2(C* v, const C* __restrict__ mm, uint32_t creg) {
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
     if (e & ((1 << KH) | (1 << KL))) continue;
-    if ((e & creg) != creg) continue;
+    if (CTRL && (e & creg) != creg) continue;
     const int i1 = e | (1 << KL), i2 = e | (1 << KH), i3 = i1 | i2;
     const C a0 = v[e], a1 = v[i1], a2 = v[i2], a3 = v[i3];
     C o[4];
@@ -914,13 +939,24 @@ __device__ __forceinline__ void r2(C* v, const C* __restrict__ mm, uint32_t creg
 
 template <typename C>
 __device__ __forceinline__ void r2_any(C* v, int kh, int kl, const C* __restrict__ mp, uint32_t creg) {
+  if (creg == 0) {  // uniform: no register-slot controls
+    switch (kh * 4 + kl) {
+      case 4: r2<1, 0, false>(v, mp, 0); break;
+      case 8: r2<2, 0, false>(v, mp, 0); break;
+      case 9: r2<2, 1, false>(v, mp, 0); break;
+      case 12: r2<3, 0, false>(v, mp, 0); break;
+      case 13: r2<3, 1, false>(v, mp, 0); break;
+      default: r2<3, 2, false>(v, mp, 0); break;
+    }
+    return;
+  }
   switch (kh * 4 + kl) {
-    case 4: r2<1, 0>(v, mp, creg); break;
-    case 8: r2<2, 0>(v, mp, creg); break;
-    case 9: r2<2, 1>(v, mp, creg); break;
-    case 12: r2<3, 0>(v, mp, creg); break;
-    case 13: r2<3, 1>(v, mp, creg); break;
-    default: r2<3, 2>(v, mp, creg); break;
+    case 4: r2<1, 0, true>(v, mp, creg); break;
+    case 8: r2<2, 0, true>(v, mp, creg); break;
+    case 9: r2<2, 1, true>(v, mp, creg); break;
+    case 12: r2<3, 0, true>(v, mp, creg); break;
+    case 13: r2<3, 1, true>(v, mp, creg); break;
+    default: r2<3, 2, true>(v, mp, creg); break;
   }
 }
 
@@ -941,6 +977,42 @@ __device__ __forceinline__ void rk(C* v, const double* mp, uint32_t creg) {
       for (int c = 0; c < D; ++c) acc = cmadd(acc, ldm<C>(mp, r * D + c), in[c]);
       v[g0 + r] = acc;
     }
+  }
+}
+
+// negate where `bit` is 1 (flip the sign bits, no branch)
+__device__ __forceinline__ float2 flip_sign(float2 a, uint32_t bit) {
+  const uint32_t m = bit << 31;
+  a.x = __uint_as_float(__float_as_uint(a.x) ^ m);
+  a.y = __uint_as_float(__float_as_uint(a.y) ^ m);
+  return a;
+}
+__device__ __forceinline__ double2 flip_sign(double2 a, uint32_t bit) {
+  const unsigned long long m = (unsigned long long)bit << 63;
+  a.x = __longlong_as_double(__double_as_longlong(a.x) ^ m);
+  a.y = __longlong_as_double(__double_as_longlong(a.y) ^ m);
+  return a;
+}
+
+// uncontrolled ops with compile-time register slots (the fast dispatch)
+template <int K, bool REAL, bool TWO, typename C>
+__device__ __forceinline__ void op1(C* v, C* w, const C* __restrict__ mp) {
+  const C a = mp[0], b = mp[1], c = mp[2], d = mp[3];
+  r1<K, REAL, false>(v, a, b, c, d, 0u);
+  if (TWO) r1<K, REAL, false>(w, a, b, c, d, 0u);
+}
+template <int KH, int KL, bool TWO, typename C>
+__device__ __forceinline__ void op2(C* v, C* w, const C* __restrict__ mp) {
+  r2<KH, KL, false>(v, mp, 0u);
+  if (TWO) r2<KH, KL, false>(w, mp, 0u);
+}
+template <bool TWO, typename C>
+__device__ __forceinline__ void apply_signs(C* v, C* w, uint32_t S) {
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const uint32_t bit = (S >> e) & 1u;
+    v[e] = flip_sign(v[e], bit);
+    if (TWO) w[e] = flip_sign(w[e], bit);
   }
 }
 
@@ -1001,6 +1073,9 @@ struct PassSmem {
   int hb[kMaxTileBits];
   int kpos[kMaxKBits];
   double gacc[kMaxGradPerPass][kThreads / 64];  // adjoint partials of this pass, per wave
+  // exp(i phNu[p][b]) for the tile bits b and exp(i phA[p]) at b = kMaxTileBits,
+  // stored in the state precision in the first half of each slot
+  double2 en[kMaxPhasePerPass][kMaxTileBits + 1];
 };
 
 // One staged pass over tiles t_first, t_first + t_step, ... < ntiles; the
@@ -1016,7 +1091,8 @@ __device__ __forceinline__ void pass_body(
     const typename CT<R>::C* __restrict__ matc, const PhaseRec* __restrict__ phases,
     const int32_t* __restrict__ phlist, const double* __restrict__ dpool, const double* __restrict__ btab,
     const typename CT<R>::C* __restrict__ qtab, const double* __restrict__ qang,
-    const double* __restrict__ scales, double* __restrict__ gpart, int64_t gstride, int gcol,
+    const double* __restrict__ scales, const typename CT<R>::C* __restrict__ ctab, double* __restrict__ gpart,
+    int64_t gstride, int gcol,
     int64_t t_first, int64_t t_step, int64_t ntiles, int gbits, PassSmem& sm, char* smem) {
   using C = typename CT<R>::C;
   using VT = typename CT<R>::V;
@@ -1130,13 +1206,17 @@ __device__ __forceinline__ void pass_body(
 #pragma unroll
           for (int j = 0; j < kMaxKBits; ++j)
             if ((kk >> j) & 1) s += kt[b * kMaxKBits + j];
-          phNu[p][b] = phNu0[p][b] + scl * s;
+          const double a = phNu0[p][b] + scl * s;
+          phNu[p][b] = a;
+          *reinterpret_cast<C*>(&sm.en[p][b]) = expi<C>(a);
         } else if (b == 15) {
           double s = phA0[p];
 #pragma unroll
           for (int j = 0; j < kMaxKBits; ++j)
             if ((kk >> j) & 1) s += phCk[p][j];
-          phA[p] = s + scl * kt[m * kMaxKBits + kk];
+          const double a = s + scl * kt[m * kMaxKBits + kk];
+          phA[p] = a;
+          *reinterpret_cast<C*>(&sm.en[p][kMaxTileBits]) = expi<C>(a);
         }
       }
       __syncthreads();
@@ -1144,32 +1224,178 @@ __device__ __forceinline__ void pass_body(
 
     for (int si = 0; si < nst; ++si) {
       const StageRec st = stages[st0 + (TWO ? nst - 1 - si : si)];
-      const uint32_t rm0 = 1u << st.rb[0], rm1 = 1u << st.rb[1], rm2 = 1u << st.rb[2], rm3 = 1u << st.rb[3];
-      // tile index of register element e: jg | (bits of e placed at the stage's register bits)
-      auto jr = [&](int e) {
-        return ((e & 1) ? rm0 : 0u) | ((e & 2) ? rm1 : 0u) | ((e & 4) ? rm2 : 0u) | ((e & 8) ? rm3 : 0u);
+      // register element e sits at tile index jg | jr(e), jr(e) = the bits of e
+      // placed at the stage's register bits.  The swizzle is linear over
+      // GF(2) and jg, jr(e) are disjoint, so its LDS byte offset is
+      // swz(jg) * sizeof(C) XOR sr(e), sr(e) the XOR of four uniform images.
+      constexpr uint32_t CB = sizeof(C) == 8 ? 3 : 4;
+      const uint32_t s0 = swz<R>(1u << st.rb[0]) << CB, s1 = swz<R>(1u << st.rb[1]) << CB;
+      const uint32_t s2 = swz<R>(1u << st.rb[2]) << CB, s3 = swz<R>(1u << st.rb[3]) << CB;
+      // walk the sixteen elements in Gray-code order g(i) = i ^ (i >> 1): step i
+      // flips slot bit ctz(i), i.e. XORs one of the four uniform images into
+      // the address; the empty asm keeps the chain from being folded into
+      // sixteen precomputed constants (which costs scalar registers)
+      auto step = [&](uint32_t& ad, int i) {
+        const int fb = __builtin_ctz(i);
+        ad ^= fb == 0 ? s0 : fb == 1 ? s1 : fb == 2 ? s2 : s3;
+        asm volatile("" : "+v"(ad));
       };
+      char* const b1 = reinterpret_cast<char*>(t1);
+      char* const b2 = reinterpret_cast<char*>(t2);
       for (int gb = 0; gb < (M >> NR); gb += blockDim.x) {
         const bool valid = !GUARD || gb + tid < (M >> NR);
         const uint32_t jg = valid ? insert_zeros((uint32_t)(gb + tid), st.rbmask) : 0u;
+        const int grp = valid ? gb + tid : 0;  // per-group table row (threads past the tile read row 0)
+        uint32_t A = swz<R>(jg) << CB;
         C v[NE], w[NE];
+        {
+          uint32_t ad = A;
 #pragma unroll
-        for (int e = 0; e < NE; ++e) {
-          v[e] = t1[swz<R>(jg | jr(e))];
-          if (TWO) w[e] = t2[swz<R>(jg | jr(e))];
+          for (int i = 0; i < NE; ++i) {
+            if (i) step(ad, i);
+            const int e = i ^ (i >> 1);
+            v[e] = *reinterpret_cast<const C*>(b1 + ad);
+            if (TWO) w[e] = *reinterpret_cast<const C*>(b2 + ad);
+          }
         }
+        // an empty asm that "redefines" A: the scatter recomputes its
+        // addresses instead of keeping sixteen of them live across the ops
+        asm volatile("" : "+v"(A));
+        // sign mask of a phase whose coefficients are all multiples of pi:
+        // the factor of register element e is (-1)^bit e
+        auto sign_mask = [&](const TileOp& op, const StageRec& sr, int grp, uint32_t jgl) -> uint32_t {
+          const int p = op.pidx;
+          const PhaseRec rec = phases[op.aux];
+          const double* bt = btab + rec.bt_off + grp * (NR + 1);
+          uint32_t S;
+          if (op.flags & 2u) {
+            const int kbs = op.b[0];
+            const int rbk = kbs == 0 ? sr.rb[0] : kbs == 1 ? sr.rb[1] : kbs == 2 ? sr.rb[2] : sr.rb[3];
+            S = pi_parity(phNu[p][rbk] + bt[1 + kbs]) ? slot_pattern(kbs) : 0u;
+          } else {
+            double th = phA[p] + bt[0];
+            for (uint32_t r = jgl; r; r &= r - 1) th += phNu[p][__builtin_ctz(r)];
+            S = pi_parity(th) ? 0xFFFFu : 0u;
+            if (pi_parity(phNu[p][sr.rb[0]] + bt[1])) S ^= 0xAAAAu;
+            if (pi_parity(phNu[p][sr.rb[1]] + bt[2])) S ^= 0xCCCCu;
+            if (pi_parity(phNu[p][sr.rb[2]] + bt[3])) S ^= 0xF0F0u;
+            if (pi_parity(phNu[p][sr.rb[3]] + bt[4])) S ^= 0xFF00u;
+          }
+          return S ^ (uint32_t)rec.wr_sign;
+        };
+        // general phase: factor of register element e = exp(i theta_tile) *
+        // exp(i beta_0) * prod_{tile bits r in jg} EN[r] * prod_{k in e}
+        // EN[rb_k] exp(i beta_k) * exp(i Q_R(e)), every factor from a table
+        auto phase_general = [&](const TileOp& op, const StageRec& sr, int grp, uint32_t jgl) {
+          const int p = op.pidx;
+          const PhaseRec rec = phases[op.aux];
+          const C* bc = ctab + rec.ctab_off + grp * (NR + 1);
+          const C* wc = ctab + rec.ctab_off + (rec.ctab_n - NE);
+          auto EN = [&](int b) { return *reinterpret_cast<const C*>(&sm.en[p][b]); };
+          auto B = [&](int k) { return TWO ? cconj(bc[k]) : bc[k]; };
+          const bool wtriv = rec.wr_trivial != 0;
+          C f = cmul(EN(kMaxTileBits), B(0));
+          for (uint32_t r = jgl; r; r &= r - 1) f = cmul(f, EN(__builtin_ctz(r)));
+          const C F0 = cmul(EN(sr.rb[0]), B(1));
+          const C F1 = cmul(EN(sr.rb[1]), B(2));
+          const C F2 = cmul(EN(sr.rb[2]), B(3));
+          const C F3 = cmul(EN(sr.rb[3]), B(4));
+          auto apply = [&](int e, C fe) {
+            if (!wtriv) fe = cmul(fe, TWO ? cconj(wc[e]) : wc[e]);
+            v[e] = cmul(v[e], fe);
+            if (TWO) w[e] = cmul(w[e], fe);
+          };
+          // Gray-code order with one running factor: each step sets a bit
+          // (times F_k) or clears one (times conj F_k, |F_k| = 1)
+          apply(0, f);
+          f = cmul(f, F0); apply(1, f);
+          f = cmul(f, F1); apply(3, f);
+          f = cmul(f, cconj(F0)); apply(2, f);
+          f = cmul(f, F2); apply(6, f);
+          f = cmul(f, F0); apply(7, f);
+          f = cmul(f, cconj(F1)); apply(5, f);
+          f = cmul(f, cconj(F0)); apply(4, f);
+          f = cmul(f, F3); apply(12, f);
+          f = cmul(f, F0); apply(13, f);
+          f = cmul(f, F1); apply(15, f);
+          f = cmul(f, cconj(F0)); apply(14, f);
+          f = cmul(f, cconj(F2)); apply(10, f);
+          f = cmul(f, F0); apply(11, f);
+          f = cmul(f, cconj(F1)); apply(9, f);
+          f = cmul(f, cconj(F0)); apply(8, f);
+        };
+        // every term holds register slot KBS: factor 1 where that bit is 0
+        auto phase_single = [&](const TileOp& op, const StageRec& sr, int grp, auto kbs_c) {
+          constexpr int KBS = decltype(kbs_c)::value;
+          const int p = op.pidx;
+          const PhaseRec rec = phases[op.aux];
+          const C* bc = ctab + rec.ctab_off + grp * (NR + 1);
+          const C* wc = ctab + rec.ctab_off + (rec.ctab_n - NE);
+          const C b = TWO ? cconj(bc[1 + KBS]) : bc[1 + KBS];
+          const C F = cmul(*reinterpret_cast<const C*>(&sm.en[p][sr.rb[KBS]]), b);
+          const bool wtriv = rec.wr_trivial != 0;
+#pragma unroll
+          for (int e = 0; e < NE; ++e) {
+            if (!((e >> KBS) & 1)) continue;
+            const C fe = wtriv ? F : cmul(F, TWO ? cconj(wc[e]) : wc[e]);
+            v[e] = cmul(v[e], fe);
+            if (TWO) w[e] = cmul(w[e], fe);
+          }
+        };
         for (int oi = 0; oi < st.nops; ++oi) {
           const int o = op0 + st.op0 + (TWO ? st.nops - 1 - oi : oi);
           const int kind = ops[o].kind;
-          const bool act = valid && ((base & ops[o].cout) == ops[o].cout) && ((jg & ops[o].cin) == ops[o].cin);
-          const uint32_t creg = ops[o].creg;
+          const uint32_t cin = ops[o].cin, creg = ops[o].creg;
+          const bool uact = (base & ops[o].cout) == ops[o].cout;  // uniform
+          bool act = valid && uact;
+          if (cin) act = act && ((jg & cin) == cin);
+          if (TWO && kind == OP_ROT && ops[o].gslot >= 0) {
+            double pg = act ? rgrad_any(v, w, ops[o].b[0], creg, ops[o].pauli) : 0.0;
+            for (int off = 32; off > 0; off >>= 1) pg += __shfl_xor(pg, off, 64);
+            if ((tid & 63) == 0) sm.gacc[ops[o].aux][tid >> 6] += pg;
+          }
+          if (!uact) continue;
+          if (cin == 0 && creg == 0) {
+            // one flat switch over a uniform opcode with compile-time slots:
+            // straight-line cases keep the register array in place
+            int opc;
+            if (kind == OP_DENSE1 || kind == OP_ROT) opc = ((ops[o].flags & 1u) ? 4 : 0) + ops[o].b[0];
+            else if (kind == OP_DENSE2) {
+              const int kh = ops[o].b[0], kl = ops[o].b[1];
+              opc = 8 + (kh == 1 ? 0 : kh == 2 ? 1 + kl : 3 + kl);
+            } else if (kind == OP_PHASE && (ops[o].flags & 4u)) opc = 14;
+            else if (kind == OP_PHASE) opc = (ops[o].flags & 2u) ? 20 + ops[o].b[0] : 19;
+            else opc = -1;
+            const C* m1 = matc + ops[o].mat + (TWO ? 4 : 0);
+            const C* m2 = matc + ops[o].mat + (TWO ? 16 : 0);
+            switch (opc) {
+              case 0: op1<0, false, TWO>(v, w, m1); break;
+              case 1: op1<1, false, TWO>(v, w, m1); break;
+              case 2: op1<2, false, TWO>(v, w, m1); break;
+              case 3: op1<3, false, TWO>(v, w, m1); break;
+              case 4: op1<0, true, TWO>(v, w, m1); break;
+              case 5: op1<1, true, TWO>(v, w, m1); break;
+              case 6: op1<2, true, TWO>(v, w, m1); break;
+              case 7: op1<3, true, TWO>(v, w, m1); break;
+              case 8: op2<1, 0, TWO>(v, w, m2); break;
+              case 9: op2<2, 0, TWO>(v, w, m2); break;
+              case 10: op2<2, 1, TWO>(v, w, m2); break;
+              case 11: op2<3, 0, TWO>(v, w, m2); break;
+              case 12: op2<3, 1, TWO>(v, w, m2); break;
+              case 13: op2<3, 2, TWO>(v, w, m2); break;
+              case 14: apply_signs<TWO>(v, w, sign_mask(ops[o], st, grp, jg)); break;
+              case 19: phase_general(ops[o], st, grp, jg); break;
+              case 20: phase_single(ops[o], st, grp, std::integral_constant<int, 0>()); break;
+              case 21: phase_single(ops[o], st, grp, std::integral_constant<int, 1>()); break;
+              case 22: phase_single(ops[o], st, grp, std::integral_constant<int, 2>()); break;
+              case 23: phase_single(ops[o], st, grp, std::integral_constant<int, 3>()); break;
+              default: break;
+            }
+            continue;
+          }
+          // controlled ops (register-slot or in-tile controls): predicated per thread
           if (kind == OP_DENSE1 || kind == OP_ROT) {
             const int k = ops[o].b[0];
-            if (TWO && kind == OP_ROT && ops[o].gslot >= 0) {
-              double pg = act ? rgrad_any(v, w, k, creg, ops[o].pauli) : 0.0;
-              for (int off = 32; off > 0; off >>= 1) pg += __shfl_xor(pg, off, 64);
-              if ((tid & 63) == 0) sm.gacc[ops[o].aux][tid >> 6] += pg;
-            }
             if (!act) continue;
             const C* mp = matc + ops[o].mat + (TWO ? 4 : 0);
             const C a = mp[0], b = mp[1], c = mp[2], d = mp[3];
@@ -1185,86 +1411,16 @@ __device__ __forceinline__ void pass_body(
             const C* mp = matc + ops[o].mat + (TWO ? 16 : 0);
             r2_any(v, ops[o].b[0], ops[o].b[1], mp, creg);
             if (TWO) r2_any(w, ops[o].b[0], ops[o].b[1], mp, creg);
-          } else if (kind == OP_PHASE && (ops[o].flags & 2u)) {
-            // every term holds register slot kb: the factor is 1 where that bit
-            // is 0, and exp(i beta_kb) * wr[e] where it is 1
-            if (!act) continue;
-            const int p = ops[o].pidx, kbs = ops[o].b[0];
-            const PhaseRec rec = phases[ops[o].aux];
-            const double scl = (rec.scale_idx >= 0 ? scales[rec.scale_idx] : 1.0) * (TWO ? -1.0 : 1.0);
-            const double* bt = btab + rec.bt_off + (gb + tid) * (NR + 1);
-            const int rbk = kbs == 0 ? st.rb[0] : kbs == 1 ? st.rb[1] : kbs == 2 ? st.rb[2] : st.rb[3];
-            const C F = expi<C>(phNu[p][rbk] + scl * bt[1 + kbs]);
-            const C* qt = qtab + rec.wr_off;
-            const bool wtriv = rec.wr_trivial != 0, wscaled = rec.scale_idx >= 0;
-            const double* qa = qang + rec.wr_off;
-#pragma unroll
-            for (int e = 0; e < NE; ++e) {
-              if (!((e >> kbs) & 1)) continue;
-              C fe = F;
-              if (!wtriv) {
-                C wr;
-                if (wscaled) wr = expi<C>(scl * qa[e]);
-                else wr = TWO ? cconj(qt[e]) : qt[e];
-                fe = cmul(fe, wr);
-              }
-              v[e] = cmul(v[e], fe);
-              if (TWO) w[e] = cmul(w[e], fe);
-            }
-          } else if (kind == OP_PHASE) {
-            if (!act) continue;
-            const int p = ops[o].pidx;
-            const PhaseRec rec = phases[ops[o].aux];
-            const double scl = (rec.scale_idx >= 0 ? scales[rec.scale_idx] : 1.0) * (TWO ? -1.0 : 1.0);
-            const double* bt = btab + rec.bt_off + (gb + tid) * (NR + 1);
-            double th = phA[p] + scl * bt[0];
-            for (uint32_t r = jg; r; r &= r - 1) th += phNu[p][__builtin_ctz(r)];
-            // factor of register element e: exp(i th) * prod_{k in e} F_k * wr[e],
-            // walked in Gray-code order with one running product
-            const C F0 = expi<C>(phNu[p][st.rb[0]] + scl * bt[1]);
-            const C F1 = expi<C>(phNu[p][st.rb[1]] + scl * bt[2]);
-            const C F2 = expi<C>(phNu[p][st.rb[2]] + scl * bt[3]);
-            const C F3 = expi<C>(phNu[p][st.rb[3]] + scl * bt[4]);
-            const C* qt = qtab + rec.wr_off;
-            // factor of register element e = exp(i th) * prod_{k in e} F_k (* wr[e]),
-            // visited in Gray-code order with one running factor: each step
-            // sets a bit (times F_k) or clears one (times conj F_k, |F_k| = 1)
-            const bool wtriv = rec.wr_trivial != 0;
-            const bool wscaled = rec.scale_idx >= 0;
-            auto apply = [&](int e, C fe) {
-              if (!wtriv) {
-                C wr;
-                if (wscaled) wr = expi<C>(scl * qang[rec.wr_off + e]);
-                else wr = TWO ? cconj(qt[e]) : qt[e];
-                fe = cmul(fe, wr);
-              }
-              v[e] = cmul(v[e], fe);
-              if (TWO) w[e] = cmul(w[e], fe);
-            };
-            C f = expi<C>(th);
-            apply(0, f);
-            f = cmul(f, F0); apply(1, f);
-            f = cmul(f, F1); apply(3, f);
-            f = cmul(f, cconj(F0)); apply(2, f);
-            f = cmul(f, F2); apply(6, f);
-            f = cmul(f, F0); apply(7, f);
-            f = cmul(f, cconj(F1)); apply(5, f);
-            f = cmul(f, cconj(F0)); apply(4, f);
-            f = cmul(f, F3); apply(12, f);
-            f = cmul(f, F0); apply(13, f);
-            f = cmul(f, F1); apply(15, f);
-            f = cmul(f, cconj(F0)); apply(14, f);
-            f = cmul(f, cconj(F2)); apply(10, f);
-            f = cmul(f, F0); apply(11, f);
-            f = cmul(f, cconj(F1)); apply(9, f);
-            f = cmul(f, cconj(F0)); apply(8, f);
           }
         }
         if (valid) {
+          uint32_t ad = A;
 #pragma unroll
-          for (int e = 0; e < NE; ++e) {
-            t1[swz<R>(jg | jr(e))] = v[e];
-            if (TWO) t2[swz<R>(jg | jr(e))] = w[e];
+          for (int i = 0; i < NE; ++i) {
+            if (i) step(ad, i);
+            const int e = i ^ (i >> 1);
+            *reinterpret_cast<C*>(b1 + ad) = v[e];
+            if (TWO) *reinterpret_cast<C*>(b2 + ad) = w[e];
           }
         }
       }
@@ -1302,11 +1458,12 @@ __global__ __launch_bounds__(256) void k_tile2(
     const typename CT<R>::C* __restrict__ matc, const PhaseRec* __restrict__ phases,
     const int32_t* __restrict__ phlist, const double* __restrict__ dpool, const double* __restrict__ btab,
     const typename CT<R>::C* __restrict__ qtab, const double* __restrict__ qang,
-    const double* __restrict__ scales, double* __restrict__ gpart, int64_t ntiles) {
+    const double* __restrict__ scales, const typename CT<R>::C* __restrict__ ctab, double* __restrict__ gpart,
+    int64_t ntiles) {
   extern __shared__ __align__(16) char smem[];
   __shared__ PassSmem sm;
   pass_body<R, TWO, NLD, false>(psi, lam, g, ops, stages, matc, phases, phlist, dpool, btab, qtab, qang, scales,
-                                gpart, kGradStride, blockIdx.x * 4, blockIdx.x, gridDim.x, ntiles,
+                                ctab, gpart, kGradStride, blockIdx.x * 4, blockIdx.x, gridDim.x, ntiles,
                                 __builtin_ctz(gridDim.x), sm, smem);
 }
 
@@ -1477,6 +1634,7 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
   const int tid = threadIdx.x;
   C* matc = reinterpret_cast<C*>(a.dp.matc);
   const C* qtab = reinterpret_cast<const C*>(a.dp.qtab);
+  const C* ctab = reinterpret_cast<const C*>(a.dp.ctab);
   for (;;) {
     if (tid == 0) cur = atomicAdd(a.counter, 1);
     __syncthreads();
@@ -1521,12 +1679,14 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
           pass_body<R, false, NLD, true>(psi, nullptr, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
                                          matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
                                          a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
-                                         a.dp.qang + in.qt_base, nullptr, gp, 4, 0, 0, 1, nt, 0, sm, smem);
+                                         a.dp.qang + in.qt_base, nullptr, ctab + in.ct_base, gp, 4, 0, 0, 1, nt,
+                                         0, sm, smem);
         else
           pass_body<R, true, NLD, true>(psi, lam, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
                                         matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
                                         a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
-                                        a.dp.qang + in.qt_base, nullptr, gp, 4, 0, 0, 1, nt, 0, sm, smem);
+                                        a.dp.qang + in.qt_base, nullptr, ctab + in.ct_base, gp, 4, 0, 0, 1, nt, 0,
+                                        sm, smem);
       }
     }
     // gradient of every parameter, slots in order (deterministic)
@@ -1539,6 +1699,23 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
       }
     }
     __syncthreads();
+  }
+}
+
+// the unit factors of scaled phase records: exp(i s angle), s = scales[rec.scale_idx];
+// one workgroup per phase record
+template <typename R>
+__global__ void k_phase_tabs(const PhaseRec* __restrict__ phases, const double* __restrict__ btab,
+                             const double* __restrict__ qang, const double* __restrict__ scales,
+                             typename CT<R>::C* __restrict__ ctab) {
+  using C = typename CT<R>::C;
+  const PhaseRec rec = phases[blockIdx.x];
+  if (rec.scale_idx < 0 || rec.ctab_off < 0) return;
+  const double sc = scales[rec.scale_idx];
+  const int nb = rec.ctab_n - NE;
+  for (int i = threadIdx.x; i < rec.ctab_n; i += blockDim.x) {
+    const double a = i < nb ? btab[rec.bt_off + i] : qang[rec.wr_off + (i - nb)];
+    ctab[rec.ctab_off + i] = expi<C>(sc * a);
   }
 }
 
@@ -1590,11 +1767,11 @@ hipError_t launch_tile2_t(void* psi, void* psi2, const PassGeom& g, const DevPla
   if (two)
     hipLaunchKernelGGL((k_tile2<R, true, NLD>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, (C*)psi2, g, dp.ops,
                        dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab, (const C*)dp.qtab,
-                       dp.qang, scales, gpart, nt);
+                       dp.qang, scales, (const C*)dp.ctab, gpart, nt);
   else
     hipLaunchKernelGGL((k_tile2<R, false, NLD>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, nullptr, g, dp.ops,
                        dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab, (const C*)dp.qtab,
-                       dp.qang, scales, gpart, nt);
+                       dp.qang, scales, (const C*)dp.ctab, gpart, nt);
   return hipGetLastError();
 }
 
@@ -1662,6 +1839,17 @@ hipError_t launch_tile_pass(bool dbl, void* psi, void* psi2, const PassGeom& g, 
       hipLaunchKernelGGL((k_tile<float, false>), dim3(grid), dim3(kThreads), lds, s, (float2*)psi, nullptr, g,
                          dp, params, scales, gpart, nt);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_phase_tabs(bool dbl, const DevPlan& dp, const double* scales, hipStream_t s) {
+  if (dp.nphases <= 0 || !scales) return hipSuccess;
+  if (dbl)
+    hipLaunchKernelGGL((k_phase_tabs<double>), dim3(dp.nphases), dim3(256), 0, s, dp.phases, dp.btab, dp.qang, scales,
+                       (double2*)dp.ctab);
+  else
+    hipLaunchKernelGGL((k_phase_tabs<float>), dim3(dp.nphases), dim3(256), 0, s, dp.phases, dp.btab, dp.qang, scales,
+                       (float2*)dp.ctab);
   return hipGetLastError();
 }
 

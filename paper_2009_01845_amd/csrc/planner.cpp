@@ -24,6 +24,7 @@ namespace qs {
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.141592653589793238462643383279;
 
 bool is_diag(const std::vector<cd>& m, int dim) {
   for (int r = 0; r < dim; ++r)
@@ -58,7 +59,7 @@ std::vector<cd> dagger(const std::vector<cd>& a, int dim) {
   return o;
 }
 
-enum BKind { BK_DENSE = 0, BK_ROT = 1, BK_PHASE = 2 };
+enum BKind { BK_DENSE = 0, BK_ROT = 1, BK_PHASE = 2, BK_SPHASE = 3 };
 
 struct Term {  // theta contribution: ang * x_p * x_q (p == q: linear)
   int p, q;
@@ -78,6 +79,8 @@ struct BitGate {
   uint64_t nmask = 0;  // bits where the gate is not diagonal
   uint64_t dmask = 0;  // bits where it is diagonal (controls, diagonal targets)
   bool mfma = false;   // applied as a dense block on matrix cores (own pass)
+  const PhasePoly* spoly = nullptr;  // BK_SPHASE: run-time scaled phase
+  int scale_slot = -1;
 };
 
 // Pending op inside an open pass, in global bit terms.
@@ -159,6 +162,14 @@ std::vector<cd> expand_controls(const std::vector<cd>& G, int k, int nc) {
 // Convert a user gate to index bits under the current relabelling.
 BitGate to_bits(const Gate& g, int n, const std::vector<int>& phys, const TuneOpts& opts) {
   BitGate b;
+  if (g.spoly) {  // diagonal on every bit of its polynomial (index bits already)
+    b.kind = BK_SPHASE;
+    b.spoly = g.spoly;
+    b.scale_slot = g.scale_slot;
+    b.dmask = g.spoly->support();
+    if (!b.dmask) b.dmask = 1;  // a constant still orders against nothing but keeps a bit
+    return b;
+  }
   b.k = g.k;
   for (int i = 0; i < g.k; ++i) b.tb[i] = phys[g.tq[i]];
   for (int q : g.cq) b.cmask |= 1ull << phys[q];
@@ -295,6 +306,9 @@ TileOp make_phase_op(Plan& plan, const PassGeom& g, const PhasePoly& P, int scal
   rec.bt_off = -1;
   rec.wr_trivial = 0;
   rec.kt_off = -1;
+  rec.wr_sign = 0;
+  rec.ctab_off = -1;
+  rec.ctab_n = 0;
   const int M = 1 << g.m;
   std::vector<double> ang(M, 0.0);
   for (int j = 1; j < M; ++j) {  // ang[j] = ang[j without its top bit] + the top bit's terms
@@ -482,6 +496,25 @@ void stage_pass(Plan& plan, Pass& ps) {
           plan.qang.push_back(rec.scale_idx < 0 ? wrap_angle(q) : q);
         }
         rec.wr_trivial = trivial ? 1 : 0;
+        // a fixed phase whose coefficients are all multiples of pi (CZ, Z and
+        // CZ-layer terms) only flips signs: keep the parity of Q_R(e)
+        rec.wr_sign = 0;
+        if (rec.scale_idx < 0) {
+          auto pi_mult = [](double v) {
+            const double r = v / kPi;
+            return std::fabs(r - std::nearbyint(r)) < 1e-9;
+          };
+          bool sign = pi_mult(plan.dpool[rec.dpool]);
+          for (int p2 = 0; p2 < n && sign; ++p2) {
+            sign &= pi_mult(mu[p2]);
+            for (int q2 = p2 + 1; q2 < n && sign; ++q2) sign &= pi_mult(lam[size_t(p2) * n + q2]);
+          }
+          if (sign) {
+            op.flags |= 4u;
+            for (int e = 0; e < (1 << kRegBits); ++e)
+              if ((long long)std::llround(plan.qang[rec.wr_off + e] / kPi) & 1) rec.wr_sign |= 1 << e;
+          }
+        }
         // does every term of theta contain one register bit (a phase that is
         // 1 wherever that bit is 0)?
         for (int k = 0; k < kRegBits && !(op.flags & 2u); ++k) {
@@ -540,6 +573,14 @@ void stage_pass(Plan& plan, Pass& ps) {
             plan.btab.push_back(b);
           }
         }
+        // the same angles as unit complex factors (left zero for a scaled
+        // record: its scale is known per launch)
+        rec.ctab_off = (int)plan.ctab.size();
+        rec.ctab_n = ngr * (kRegBits + 1) + (1 << kRegBits);
+        for (int i = 0; i < ngr * (kRegBits + 1); ++i)
+          plan.ctab.push_back(rec.scale_idx < 0 ? std::polar(1.0, plan.btab[rec.bt_off + i]) : cd(0, 0));
+        for (int e = 0; e < (1 << kRegBits); ++e)
+          plan.ctab.push_back(rec.scale_idx < 0 ? plan.qtab[rec.wr_off + e] : cd(0, 0));
       }
       if (op.kind != OP_PHASE) op.flags = 0;
       if (op.kind == OP_ROT && op.pauli == 2) op.flags |= 1u;
@@ -690,7 +731,7 @@ std::vector<Gate> fuse_gates(const std::vector<Gate>& in, int K) {
     U.clear();
   };
   for (const Gate& g : in) {
-    if (g.is_rot) {
+    if (g.is_rot || g.spoly) {
       flush();
       out.push_back(g);
       continue;
@@ -900,6 +941,21 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
           ++placed;
           continue;
         }
+        if (b.kind == BK_SPHASE) {  // its own phase op, scaled per launch
+          if (nphase_raw(raw) >= kMaxPhasePerPass - 2) {
+            ++it;
+            continue;
+          }
+          RawOp ro;
+          ro.kind = OP_PHASE;
+          ro.poly = *b.spoly;
+          ro.scale_idx = b.scale_slot;
+          raw.push_back(std::move(ro));
+          finish(g, it);
+          progress = true;
+          ++placed;
+          continue;
+        }
         if (b.mfma) {  // placed between tiled passes below
           ++it;
           continue;
@@ -922,8 +978,11 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
           continue;
         }
         for (int bit : need) hsel.insert(bit);
-        if (b.nmask) {
-          PhasePoly Q = extract_terms(P, n, b.nmask, false);
+        if (b.nmask && (b.nmask & P.support())) {
+          // every pending term comes from a diagonal gate whose predecessors
+          // are all placed, so applying all of them here is exact and leaves
+          // fewer, fuller phase ops than flushing only the gate's bits
+          PhasePoly Q = extract_terms(P, n, ~0ull, false);
           if (!Q.empty) {
             RawOp ro;
             ro.kind = OP_PHASE;
@@ -1046,6 +1105,28 @@ Plan plan_rx_layer(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly)
     hc.gates.push_back(g);
   }
   hc.tail_phase = poly;
+  return plan_circuit(hc, opts, dbl);
+}
+
+Plan plan_trotter(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly, int steps) {
+  HostCircuit hc;
+  hc.n = n;
+  hc.nparams = steps;
+  for (int s = 0; s < steps; ++s) {
+    for (int q = 0; q < n; ++q) {
+      Gate g;
+      g.k = 1;
+      g.tq[0] = q;
+      g.is_rot = true;
+      g.pauli = 'X';
+      g.pidx = s;
+      hc.gates.push_back(g);
+    }
+    Gate ph;
+    ph.spoly = poly;
+    ph.scale_slot = s;
+    hc.gates.push_back(ph);
+  }
   return plan_circuit(hc, opts, dbl);
 }
 

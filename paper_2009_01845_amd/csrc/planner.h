@@ -19,6 +19,10 @@ struct Gate {
   char pauli = 0;
   int pidx = -1;
   std::vector<cd> mat;  // 2^k x 2^k row-major, MAT gates only
+  // a diagonal exp(i scales[scale_slot] * E(x)) with E a polynomial owned by
+  // the caller (adiabatic steps); k and the target list are unused
+  const struct PhasePoly* spoly = nullptr;
+  int scale_slot = -1;
 };
 
 struct TuneOpts {
@@ -46,6 +50,18 @@ struct PhasePoly {
   std::vector<double> lam;  // n*n symmetric, zero diagonal
   bool empty = true;
   void init(int n) { mu.assign(n, 0.0); lam.assign(size_t(n) * n, 0.0); c = 0.0; empty = true; }
+  // index bits that appear in a non-constant term
+  uint64_t support() const {
+    if (empty) return 0;
+    const int n = (int)mu.size();
+    uint64_t s = 0;
+    for (int p = 0; p < n; ++p) {
+      if (mu[p] != 0.0) s |= 1ull << p;
+      for (int q = p + 1; q < n; ++q)
+        if (lam[size_t(p) * n + q] != 0.0) s |= (1ull << p) | (1ull << q);
+    }
+    return s;
+  }
 };
 
 struct Plan {
@@ -57,6 +73,7 @@ struct Plan {
   std::vector<PhaseRec> phases;
   std::vector<cd> qtab;          // exp(i theta_T(j)) per phase op
   std::vector<double> qang;      // theta_T(j) per phase op (same offsets as qtab)
+  std::vector<cd> ctab;          // per-thread-group phase factors of staged phase ops
   std::vector<StageRec> stages;  // staged passes
   std::vector<int32_t> phlist;   // staged passes: phase record of each per-pass phase slot
   std::vector<double> btab;      // staged passes: per-group phase constants (PhaseRec::bt_off)
@@ -94,6 +111,9 @@ TileOp make_phase_op(Plan& plan, const PassGeom& g, const PhasePoly& P, int scal
 PhasePoly ising_poly(int n, const double* J, const double* h);
 // RX(params[0]) on every qubit, optionally followed by exp(i scales[0] E(x)).
 Plan plan_rx_layer(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly);
+// `steps` Trotter steps in one plan: for s = 0..steps-1, RX(params[s]) on every
+// qubit then exp(i scales[s] E(x)); consecutive steps share passes.
+Plan plan_trotter(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly, int steps);
 
 // Greedy fusion of consecutive fixed gates into blocks of at most K qubits.
 std::vector<Gate> fuse_gates(const std::vector<Gate>& in, int K);

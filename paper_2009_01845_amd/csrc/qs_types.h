@@ -40,7 +40,8 @@ struct TileOp {
                      // OP_ROT with a gradient slot: its index among the pass's gradient ops
   int32_t gslot;     // adjoint: gradient slot of this op (-1 if none)
   uint32_t creg;     // staged passes: control mask over register slots
-  uint32_t flags;    // bit 0: the matrix is real; bit 1 (OP_PHASE): every term holds register slot b[0]
+  uint32_t flags;    // bit 0: the matrix is real; bit 1 (OP_PHASE): every term holds register slot b[0];
+                     // bit 2 (OP_PHASE): every coefficient is a multiple of pi (factors are +-1)
 };
 
 constexpr int kRegBits = 4;            // register slots per thread in a staged pass
@@ -76,6 +77,10 @@ struct PhaseRec {
   int32_t bt_off;    // staged passes: per thread group (theta_T(jg), beta_0..beta_3) pass constants
   int32_t wr_trivial;  // 1 when Q_R(e) is zero for every e
   int32_t kt_off;    // staged passes: lam(tile bit b, k-bit j) [m][kMaxKBits], then Q_k(kk) [2^kb]
+  int32_t wr_sign;   // sign ops: bit e = parity of Q_R(e) / pi
+  int32_t ctab_off;  // staged passes: complex factors in the state precision, per thread group
+                     // exp(i beta_0..4) [ngroups][kRegBits + 1], then exp(i Q_R(e)) [2^kRegBits]
+  int32_t ctab_n;    // entries at ctab_off (scaled records are filled per launch)
 };
 
 // Per-pass geometry.

@@ -175,6 +175,32 @@ def test_expectation_and_norm(api, dt):
 
 
 @pytest.mark.parametrize("dt", DTS)
+def test_sign_only_phases_ry_cz_ring(api, dt):
+    # CZ rings, CZ pairs and Z gates only flip signs: the planner marks such
+    # phase ops and the kernel applies them as parity masks
+    n = 16
+    banner("sign phases", dt)
+    rng = np.random.default_rng(21)
+    _, spec, params, terms = qsynth.gradient_20q(seed=5, n=n, layers=4)
+    extra = [qsynth.gate("Z", (int(q),)) for q in rng.integers(0, n, 5)]
+    extra += [qsynth.gate("Z", (int(a),), (int(b),)) for a, b in rng.permutation(n).reshape(-1, 2)[:4]]
+    spec = spec[: len(spec) // 2] + extra + spec[len(spec) // 2:]
+    c = api.Circuit.from_spec(n, spec)
+    st = gpu_state(api, n, dt)
+    c.run(st, params)
+    ref = ocirc.run(n, spec, None, params)
+    assert maxabs(st.download(), ref) < TOL[dt]
+    if dt == "c128":
+        from oracle import gradients as ograd
+        psi, lam = api.State(n, dt), api.State(n, dt)
+        c.run(psi, params)
+        H = api.Observable.pauli_sum(n, terms)
+        e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+        e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+        assert abs(e - e_ref) < 1e-10 and np.max(np.abs(g - g_ref)) < 1e-10
+
+
+@pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("n", [5, 15, 20])
 def test_diagonal_polynomial_expectation(api, dt, n):
     # diagonal groups with at most two Z factors per term take the polynomial
@@ -248,6 +274,23 @@ def test_adiabatic_trotter_vs_oracle(api, dt):
     st.set_plus()
     I = api.Observable.ising(n, J, h)
     e = api.adiabatic_run(st.h, I.h, 2.0, 0.05)
+    assert maxabs(st.download(), ref) < (1e-11 if dt == "c128" else 2e-5)
+    assert abs(e - oad.energy(ref, E)) < (1e-10 if dt == "c128" else 1e-4)
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_adiabatic_trotter_staged_blocks(api, dt):
+    # register-staged passes, 37 steps = four blocks of 8 shared-pass steps
+    # plus a block of 5, full random couplings
+    n = 13
+    banner("adiabatic staged", dt)
+    J, h = qsynth.ising_couplings(n, 8)
+    E = oobs.ising_energies(J, h)
+    ref = oad.trotter(n, E, 0.37, 0.01)
+    st = api.State(n, dt)
+    st.set_plus()
+    I = api.Observable.ising(n, J, h)
+    e = api.adiabatic_run(st.h, I.h, 0.37, 0.01)
     assert maxabs(st.download(), ref) < (1e-11 if dt == "c128" else 2e-5)
     assert abs(e - oad.energy(ref, E)) < (1e-10 if dt == "c128" else 1e-4)
 
