@@ -1006,6 +1006,39 @@ __device__ __forceinline__ void op2(C* v, C* w, const C* __restrict__ mp) {
   r2<KH, KL, false>(v, mp, 0u);
   if (TWO) r2<KH, KL, false>(w, mp, 0u);
 }
+// [[a, i t], [i t, a]] (a, t real: X rotations) and diagonal 2x2 on slot K
+template <int K, typename C>
+__device__ __forceinline__ void r1x(C* v, C m00, C m01) {
+  const auto a = m00.x, t = m01.y;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    if (e & (1 << K)) continue;
+    const int f = e | (1 << K);
+    const C p = v[e], q = v[f];
+    v[e].x = a * p.x - t * q.y;
+    v[e].y = a * p.y + t * q.x;
+    v[f].x = a * q.x - t * p.y;
+    v[f].y = a * q.y + t * p.x;
+  }
+}
+template <int K, typename C>
+__device__ __forceinline__ void r1d(C* v, C d0, C d1) {
+#pragma unroll
+  for (int e = 0; e < NE; ++e) v[e] = cmul(v[e], (e >> K) & 1 ? d1 : d0);
+}
+template <int K, bool TWO, typename C>
+__device__ __forceinline__ void op1x(C* v, C* w, const C* __restrict__ mp) {
+  const C a = mp[0], b = mp[1];
+  r1x<K>(v, a, b);
+  if (TWO) r1x<K>(w, a, b);
+}
+template <int K, bool TWO, typename C>
+__device__ __forceinline__ void op1d(C* v, C* w, const C* __restrict__ mp) {
+  const C a = mp[0], d = mp[3];
+  r1d<K>(v, a, d);
+  if (TWO) r1d<K>(w, a, d);
+}
+
 template <bool TWO, typename C>
 __device__ __forceinline__ void apply_signs(C* v, C* w, uint32_t S) {
 #pragma unroll
@@ -1052,6 +1085,85 @@ __device__ __forceinline__ double rgrad(const C* ps, const C* la, uint32_t creg,
   return acc;
 }
 
+// Im <lambda| P psi> over the 8 pairs of slot K, P a Pauli known at compile
+// time, accumulated in the state's precision (per thread: 16 amplitudes)
+template <int K, int PAULI, typename C>
+__device__ __forceinline__ auto rgrad_fast(const C* ps, const C* la) {
+  using T = decltype(C().x);
+  T acc = 0;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    if (e & (1 << K)) continue;
+    const int f = e | (1 << K);
+    const C p0 = ps[e], p1 = ps[f], l0 = la[e], l1 = la[f];
+    T q0r, q0i, q1r, q1i;
+    if (PAULI == 1) { q0r = p1.x; q0i = p1.y; q1r = p0.x; q1i = p0.y; }
+    else if (PAULI == 2) { q0r = p1.y; q0i = -p1.x; q1r = -p0.y; q1i = p0.x; }
+    else { q0r = p0.x; q0i = p0.y; q1r = -p1.x; q1i = -p1.y; }
+    acc += l0.x * q0i - l0.y * q0r + l1.x * q1i - l1.y * q1r;
+  }
+  return acc;
+}
+
+template <typename C>
+__device__ __forceinline__ double rgrad_fast_any(const C* ps, const C* la, int k, int pauli) {
+#define QS_RG(K)                                               \
+  case K:                                                      \
+    return pauli == 1   ? (double)rgrad_fast<K, 1>(ps, la)     \
+           : pauli == 2 ? (double)rgrad_fast<K, 2>(ps, la)     \
+                        : (double)rgrad_fast<K, 3>(ps, la);
+  switch (k) {
+    QS_RG(0)
+    QS_RG(1)
+    QS_RG(2)
+    default:
+      return pauli == 1 ? (double)rgrad_fast<3, 1>(ps, la)
+                        : pauli == 2 ? (double)rgrad_fast<3, 2>(ps, la) : (double)rgrad_fast<3, 3>(ps, la);
+  }
+#undef QS_RG
+}
+
+// sum over each 16-lane row of the wave (DPP: quad swaps, then row rotations
+// by 4 and 8), returned in every lane of the row
+__device__ __forceinline__ float row_sum(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xF, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
+  return x;
+}
+template <int CTRL> __device__ __forceinline__ double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double row_sum(double x) {
+  x += dpp_d<0xB1>(x);
+  x += dpp_d<0x4E>(x);
+  x += dpp_d<0x124>(x);
+  x += dpp_d<0x128>(x);
+  return x;
+}
+// whole-wave sum (in lane 63) from row sums held in every lane of each row:
+// lane 15 of rows 0 / 2 is added into rows 1 / 3, then lane 31 into rows 2, 3
+__device__ __forceinline__ float wave_sum_rows(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xA, 0xF, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xC, 0xF, false));
+  return x;
+}
+template <int CTRL, int ROWMASK> __device__ __forceinline__ double dpp_dm(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum_rows(double x) {
+  x += dpp_dm<0x142, 0xA>(x);
+  x += dpp_dm<0x143, 0xC>(x);
+  return x;
+}
+
 template <typename C>
 __device__ __forceinline__ double rgrad_any(const C* ps, const C* la, int k, uint32_t creg, int pauli) {
   switch (k) {
@@ -1084,7 +1196,7 @@ struct PassSmem {
 // partials are summed in LDS over the workgroup's tiles and stored once, at
 // gpart[gslot * gstride + gcol + wave] (each op owns its slot, so every entry
 // has exactly one writer).
-template <typename R, bool TWO, int NLD, bool GUARD>
+template <typename R, bool TWO, int NLD, bool GUARD, bool CTRL>
 __device__ __forceinline__ void pass_body(
     typename CT<R>::C* __restrict__ psi, typename CT<R>::C* __restrict__ lam, const PassGeom& g,
     const TileOp* __restrict__ ops, const StageRec* __restrict__ stages,
@@ -1350,16 +1462,26 @@ __device__ __forceinline__ void pass_body(
           bool act = valid && uact;
           if (cin) act = act && ((jg & cin) == cin);
           if (TWO && kind == OP_ROT && ops[o].gslot >= 0) {
-            double pg = act ? rgrad_any(v, w, ops[o].b[0], creg, ops[o].pauli) : 0.0;
-            for (int off = 32; off > 0; off >>= 1) pg += __shfl_xor(pg, off, 64);
-            if ((tid & 63) == 0) sm.gacc[ops[o].aux][tid >> 6] += pg;
+            // per-thread partial, summed across the wave with DPP; lane 63 adds
+            // the wave's total to its slot (a single writer per slot)
+            using T = decltype(C().x);
+            T pg = 0;
+            if (creg == 0 && cin == 0) {
+              if (valid) pg = (T)rgrad_fast_any(v, w, ops[o].b[0], ops[o].pauli);
+            } else if (CTRL && act) {
+              pg = (T)rgrad_any(v, w, ops[o].b[0], creg, ops[o].pauli);
+            }
+            if (!uact) pg = 0;
+            pg = wave_sum_rows(row_sum(pg));
+            if ((tid & 63) == 63) sm.gacc[ops[o].aux][tid >> 6] += (double)pg;
           }
           if (!uact) continue;
           if (cin == 0 && creg == 0) {
             // one flat switch over a uniform opcode with compile-time slots:
             // straight-line cases keep the register array in place
             int opc;
-            if (kind == OP_DENSE1 || kind == OP_ROT) opc = ((ops[o].flags & 1u) ? 4 : 0) + ops[o].b[0];
+            if (kind == OP_DENSE1 || kind == OP_ROT)
+              opc = ((ops[o].flags & 16u) ? 24 : (ops[o].flags & 8u) ? 28 : (ops[o].flags & 1u) ? 4 : 0) + ops[o].b[0];
             else if (kind == OP_DENSE2) {
               const int kh = ops[o].b[0], kl = ops[o].b[1];
               opc = 8 + (kh == 1 ? 0 : kh == 2 ? 1 + kl : 3 + kl);
@@ -1389,11 +1511,21 @@ __device__ __forceinline__ void pass_body(
               case 21: phase_single(ops[o], st, grp, std::integral_constant<int, 1>()); break;
               case 22: phase_single(ops[o], st, grp, std::integral_constant<int, 2>()); break;
               case 23: phase_single(ops[o], st, grp, std::integral_constant<int, 3>()); break;
+              case 24: op1d<0, TWO>(v, w, m1); break;
+              case 25: op1d<1, TWO>(v, w, m1); break;
+              case 26: op1d<2, TWO>(v, w, m1); break;
+              case 27: op1d<3, TWO>(v, w, m1); break;
+              case 28: op1x<0, TWO>(v, w, m1); break;
+              case 29: op1x<1, TWO>(v, w, m1); break;
+              case 30: op1x<2, TWO>(v, w, m1); break;
+              case 31: op1x<3, TWO>(v, w, m1); break;
               default: break;
             }
             continue;
           }
-          // controlled ops (register-slot or in-tile controls): predicated per thread
+          // controlled ops (register-slot or in-tile controls): predicated per
+          // thread, compiled only into the variant for passes that hold them
+          if (!CTRL) continue;
           if (kind == OP_DENSE1 || kind == OP_ROT) {
             const int k = ops[o].b[0];
             if (!act) continue;
@@ -1451,7 +1583,7 @@ __device__ __forceinline__ void pass_body(
   }
 }
 
-template <typename R, bool TWO, int NLD>
+template <typename R, bool TWO, int NLD, bool CTRL>
 __global__ __launch_bounds__(256) void k_tile2(
     typename CT<R>::C* __restrict__ psi, typename CT<R>::C* __restrict__ lam, const PassGeom g,
     const TileOp* __restrict__ ops, const StageRec* __restrict__ stages,
@@ -1462,7 +1594,7 @@ __global__ __launch_bounds__(256) void k_tile2(
     int64_t ntiles) {
   extern __shared__ __align__(16) char smem[];
   __shared__ PassSmem sm;
-  pass_body<R, TWO, NLD, false>(psi, lam, g, ops, stages, matc, phases, phlist, dpool, btab, qtab, qang, scales,
+  pass_body<R, TWO, NLD, false, CTRL>(psi, lam, g, ops, stages, matc, phases, phlist, dpool, btab, qtab, qang, scales,
                                 ctab, gpart, kGradStride, blockIdx.x * 4, blockIdx.x, gridDim.x, ntiles,
                                 __builtin_ctz(gridDim.x), sm, smem);
 }
@@ -1676,13 +1808,13 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
         const PassGeom& g = a.geoms[in.pass0 + (dir ? in.npass - 1 - k : k)];
         const int64_t nt = 1ll << (g.n - g.m);
         if (dir == 0)
-          pass_body<R, false, NLD, true>(psi, nullptr, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
+          pass_body<R, false, NLD, true, true>(psi, nullptr, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
                                          matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
                                          a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
                                          a.dp.qang + in.qt_base, nullptr, ctab + in.ct_base, gp, 4, 0, 0, 1, nt,
                                          0, sm, smem);
         else
-          pass_body<R, true, NLD, true>(psi, lam, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
+          pass_body<R, true, NLD, true, true>(psi, lam, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
                                         matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
                                         a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
                                         a.dp.qang + in.qt_base, nullptr, ctab + in.ct_base, gp, 4, 0, 0, 1, nt, 0,
@@ -1752,27 +1884,35 @@ hipError_t set_lds_fn(void* fn, size_t lds) {
 template <typename R> void* fn_tile(bool two) {
   return two ? (void*)k_tile<R, true> : (void*)k_tile<R, false>;
 }
-template <typename R, int NLD> void* fn_tile2(bool two) {
-  return two ? (void*)k_tile2<R, true, NLD> : (void*)k_tile2<R, false, NLD>;
+template <typename R, int NLD, bool CTRL> void* fn_tile2(bool two) {
+  return two ? (void*)k_tile2<R, true, NLD, CTRL> : (void*)k_tile2<R, false, NLD, CTRL>;
 }
 
+template <typename R, int NLD, bool CTRL>
+hipError_t launch_tile2_c(void* psi, void* psi2, const PassGeom& g, const DevPlan& dp, const double* scales,
+                          double* gpart, int64_t nt, int grid, size_t lds, hipStream_t s) {
+  using C = typename CT<R>::C;
+  const bool two = psi2 != nullptr;
+  hipError_t e = set_lds_fn(fn_tile2<R, NLD, CTRL>(two), lds);
+  if (e != hipSuccess) return e;
+  if (two)
+    hipLaunchKernelGGL((k_tile2<R, true, NLD, CTRL>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, (C*)psi2, g,
+                       dp.ops, dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab,
+                       (const C*)dp.qtab, dp.qang, scales, (const C*)dp.ctab, gpart, nt);
+  else
+    hipLaunchKernelGGL((k_tile2<R, false, NLD, CTRL>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, nullptr, g,
+                       dp.ops, dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab,
+                       (const C*)dp.qtab, dp.qang, scales, (const C*)dp.ctab, gpart, nt);
+  return hipGetLastError();
+}
+
+// passes without controlled ops run a variant compiled without that path
 template <typename R, int NLD>
 hipError_t launch_tile2_t(void* psi, void* psi2, const PassGeom& g, const DevPlan& dp, const double* params,
                           const double* scales, double* gpart, int64_t nt, int grid, size_t lds, hipStream_t s) {
-  using C = typename CT<R>::C;
-  const bool two = psi2 != nullptr;
-  hipError_t e = set_lds_fn(fn_tile2<R, NLD>(two), lds);
-  if (e != hipSuccess) return e;
   (void)params;
-  if (two)
-    hipLaunchKernelGGL((k_tile2<R, true, NLD>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, (C*)psi2, g, dp.ops,
-                       dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab, (const C*)dp.qtab,
-                       dp.qang, scales, (const C*)dp.ctab, gpart, nt);
-  else
-    hipLaunchKernelGGL((k_tile2<R, false, NLD>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, nullptr, g, dp.ops,
-                       dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab, (const C*)dp.qtab,
-                       dp.qang, scales, (const C*)dp.ctab, gpart, nt);
-  return hipGetLastError();
+  if (g.ctrl) return launch_tile2_c<R, NLD, true>(psi, psi2, g, dp, scales, gpart, nt, grid, lds, s);
+  return launch_tile2_c<R, NLD, false>(psi, psi2, g, dp, scales, gpart, nt, grid, lds, s);
 }
 
 }  // namespace

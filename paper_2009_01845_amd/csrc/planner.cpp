@@ -377,6 +377,7 @@ void stage_pass(Plan& plan, Pass& ps) {
   PassGeom& g = ps.geom;
   g.kern = 1;
   g.st0 = g.nst = g.ph0 = g.nph = 0;
+  g.ctrl = 0;
   if (g.m < (plan.force_stage ? kRegBits + 1 : 12)) return;
   int nph = 0;
   for (const TileOp& op : ps.ops) {
@@ -584,11 +585,25 @@ void stage_pass(Plan& plan, Pass& ps) {
       }
       if (op.kind != OP_PHASE) op.flags = 0;
       if (op.kind == OP_ROT && op.pauli == 2) op.flags |= 1u;
+      if (op.kind == OP_ROT && op.pauli == 1) op.flags |= 8u;   // [[c, -is], [-is, c]]
+      if (op.kind == OP_ROT && op.pauli == 3) op.flags |= 16u;  // diagonal
       if (dim) {
         bool real = true;
         for (int i = 0; i < dim * dim; ++i) real &= plan.matpool[op.mat + i].imag() == 0.0;
         if (real) op.flags |= 1u;
       }
+      if (op.kind == OP_DENSE1 && !(op.flags & 1u)) {
+        // forward and inverse both diagonal, or both of the form [[a, ib], [ib, a]], a and b real
+        const cd* M = plan.matpool.data() + op.mat;
+        bool diag = true, xf = true;
+        for (int w2 = 0; w2 < 2; ++w2, M += 4) {
+          diag &= M[1] == 0.0 && M[2] == 0.0;
+          xf &= M[0] == M[3] && M[0].imag() == 0.0 && M[1] == M[2] && M[1].real() == 0.0;
+        }
+        if (diag) op.flags |= 16u;
+        else if (xf) op.flags |= 8u;
+      }
+      if (op.cin != 0 || op.creg != 0) g.ctrl = 1;
       out.push_back(op);
     }
     plan.stages.push_back(sr);

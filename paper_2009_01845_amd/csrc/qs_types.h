@@ -95,6 +95,7 @@ struct PassGeom {
   int32_t kern;         // 1: one LDS sweep per op; 2: register-blocked stages
   int32_t st0, nst;     // staged passes: stage range
   int32_t ph0, nph;     // staged passes: phase records prepared per tile
+  int32_t ctrl;         // staged passes: 1 if an op has controls inside the tile (predicated path)
 };
 
 }  // namespace qs
