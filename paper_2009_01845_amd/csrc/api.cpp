@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -245,6 +246,7 @@ struct qs_circuit {
   DBuf dparams;
   DBuf gpart;
   DBuf gout;
+  DBuf eout;
   std::vector<int> slot_pidx;
 };
 
@@ -260,8 +262,13 @@ struct qs_obs {
   // every term in it has at most two Z factors: [c, mu[n], lam[n*n]] and the
   // table of its low-12-bit part (empty when not applicable)
   std::vector<double> poly, elo;
+  // every other group, packed into tile sets (one pass over the state each)
+  std::vector<PauliSet> sets;
+  std::vector<PauliGroupTile> tgroups;
+  std::vector<PauliTermTile> tterms;
+  std::vector<int> far;  // groups whose flip bits do not fit a tile
   bool dev_ok = false;
-  DBuf dflips, dgoff, dterms, dpoly, delo;
+  DBuf dflips, dgoff, dterms, dpoly, delo, dtgroups, dtterms;
   void to_device(hipStream_t s) {
     if (dev_ok) return;
     upload(dflips, flips, s);
@@ -271,6 +278,8 @@ struct qs_obs {
       upload(dpoly, poly, s);
       upload(delo, elo, s);
     }
+    upload(dtgroups, tgroups, s);
+    upload(dtterms, tterms, s);
     dev_ok = true;
   }
 };
@@ -391,24 +400,54 @@ double download_scalar(const double* dev, hipStream_t s) {
 }
 
 // Expectation into dev_out[0] (device), asynchronous.
-void expectation_dev(qs_state* s, qs_obs* o, double* dev_out) {
+// sum over the observable's parts (polynomial diagonal, tile sets), each
+// leaving one partial per workgroup in its own kGridMax-long slot; with lam,
+// also lambda = H psi.  Fixed-order sums: the result is deterministic.
+void pauli_pass(qs_state* s, qs_obs* o, void* lam, double* dev_out) {
   o->to_device(s->stream);
-  const int ng = (int)o->flips.size();
-  double* part = scratch_doubles(s, size_t(ng + 1) * kGridMax + ng + 8);
-  double* slots = part + size_t(ng) * kGridMax;
-  ProfScope pr(5, s->stream);
-  hipck(launch_zero(part, int64_t(ng) * kGridMax, s->stream), "zero");
-  for (int g = 0; g < ng; ++g) {
-    if (g == 0 && o->flips[0] == 0 && !o->poly.empty())
-      hipck(launch_expect_poly(s->dbl(), s->ptr, s->n, o->dpoly.as<double>(), o->delo.as<double>(), part, s->stream),
-            "expectation");
+  const bool poly = !o->poly.empty();
+  const int nslot = (poly ? 1 : 0) + (int)o->sets.size() + (int)o->far.size();
+  double* part = scratch_doubles(s, size_t(nslot + 1) * kGridMax + nslot + 8);
+  double* slots = part + size_t(nslot) * kGridMax;
+  hipck(launch_zero(part, int64_t(std::max(nslot, 1)) * kGridMax, s->stream), "zero");
+  int k = 0;
+  if (poly) {
+    if (lam)
+      hipck(launch_hpsi_poly(s->dbl(), s->ptr, lam, s->n, o->dpoly.as<double>(), o->delo.as<double>(), part,
+                             s->stream),
+            "H psi (diagonal)");
     else
-      hipck(launch_expect_group(s->dbl(), s->ptr, s->n, o->flips[g], o->dterms.as<PauliTermDev>() + o->goff[g],
-                                o->goff[g + 1] - o->goff[g], part + size_t(g) * kGridMax, s->stream),
-            "expectation");
+      hipck(launch_expect_poly(s->dbl(), s->ptr, s->n, o->dpoly.as<double>(), o->delo.as<double>(), part, s->stream),
+            "expectation (diagonal)");
+    ++k;
+  } else if (lam && o->sets.empty() && o->far.empty()) {
+    // an observable with no terms: lambda = 0 (one double per complex64, two per complex128)
+    hipck(launch_zero(static_cast<double*>(lam), int64_t(1) << (s->n + (s->dbl() ? 1 : 0)), s->stream), "zero");
   }
-  hipck(launch_slot_sums(part, ng, kGridMax, kGridMax, slots, s->stream), "slot sums");
-  hipck(launch_final_sum(slots, ng, dev_out, s->stream), "final sum");
+  bool written = poly;  // lambda holds a first part
+  for (size_t si = 0; si < o->sets.size(); ++si, ++k) {
+    PauliSet ps = o->sets[si];
+    ps.first = (lam && !written) ? 1 : 0;
+    written = true;
+    hipck(launch_pauli_set(s->dbl(), s->ptr, lam, ps, o->dtgroups.as<PauliGroupTile>(),
+                           o->dtterms.as<PauliTermTile>(), part + size_t(k) * kGridMax, s->stream),
+          "Pauli tile set");
+  }
+  for (size_t fi = 0; fi < o->far.size(); ++fi, ++k) {
+    const int g = o->far[fi];
+    hipck(launch_pauli_far(s->dbl(), s->ptr, lam, s->n, o->flips[g], o->dterms.as<PauliTermDev>() + o->goff[g],
+                           o->goff[g + 1] - o->goff[g], (lam && !written) ? 1 : 0, part + size_t(k) * kGridMax,
+                           s->stream),
+          "Pauli group");
+    written = true;
+  }
+  hipck(launch_slot_sums(part, std::max(nslot, 1), kGridMax, kGridMax, slots, s->stream), "slot sums");
+  hipck(launch_final_sum(slots, std::max(nslot, 1), dev_out, s->stream), "final sum");
+}
+
+void expectation_dev(qs_state* s, qs_obs* o, double* dev_out) {
+  ProfScope pr(5, s->stream);
+  pauli_pass(s, o, nullptr, dev_out);
 }
 
 // Z_p = 1 - 2 x_p on index bit p, so a diagonal group of terms with at most
@@ -452,6 +491,76 @@ void diag_poly(qs_obs* o) {
   o->elo = std::move(E);
 }
 
+// Pack the groups not handled by the polynomial path into tile sets: each set
+// has the low L = min(n, 6) bits and up to 6 high bits, enough to hold every
+// flip bit of its groups; a pass over the state evaluates the whole set.
+void pauli_sets(qs_obs* o) {
+  const int n = o->n;
+  const int L = std::min(n, 6);
+  const int Hmax = std::min(n - L, kPauliMaxH);
+  std::vector<int> todo;
+  for (int g = 0; g < (int)o->flips.size(); ++g) {
+    if (o->flips[g] == 0 && !o->poly.empty()) continue;
+    if (__builtin_popcountll(o->flips[g] >> L) > Hmax) o->far.push_back(g);
+    else todo.push_back(g);
+  }
+  // groups with the same high flip bits next to each other
+  std::stable_sort(todo.begin(), todo.end(), [&](int a, int b) { return (o->flips[a] >> L) < (o->flips[b] >> L); });
+  size_t i = 0;
+  while (i < todo.size()) {
+    std::set<int> hsel;
+    std::vector<int> members;
+    for (; i < todo.size(); ++i) {
+      std::set<int> u = hsel;
+      for (uint64_t f = o->flips[todo[i]] >> L; f; f &= f - 1) u.insert(L + __builtin_ctzll(f));
+      if ((int)u.size() > Hmax) break;
+      hsel = u;
+      members.push_back(todo[i]);
+    }
+    if (members.empty()) fail(QS_E_STATE, "internal: a Pauli flip mask does not fit a tile");
+    for (int b = L; b < n && (int)hsel.size() < Hmax; ++b) hsel.insert(b);  // fill to a full tile
+    PauliSet ps;
+    std::memset(&ps, 0, sizeof ps);
+    ps.n = n;
+    ps.L = L;
+    ps.H = (int)hsel.size();
+    ps.first = 0;
+    int k = 0;
+    int local[64];
+    for (int b = 0; b < 64; ++b) local[b] = b < L ? b : -1;
+    for (int b : hsel) {
+      local[b] = L + k;
+      ps.hbits[k++] = b;
+    }
+    ps.g0 = (int)o->tgroups.size();
+    ps.ng = (int)members.size();
+    for (int g : members) {
+      PauliGroupTile G;
+      G.fl = 0;
+      for (uint64_t f = o->flips[g]; f; f &= f - 1) G.fl |= 1u << local[__builtin_ctzll(f)];
+      G.t0 = (int)o->tterms.size();
+      G.nt = o->goff[g + 1] - o->goff[g];
+      G.pad = 0;
+      for (int t = o->goff[g]; t < o->goff[g + 1]; ++t) {
+        const PauliTermDev& T = o->terms[t];
+        PauliTermTile tt;
+        tt.zo = 0;
+        tt.zl = 0;
+        for (uint64_t z = T.zy; z; z &= z - 1) {
+          const int b = __builtin_ctzll(z);
+          if (local[b] >= 0) tt.zl |= 1u << local[b];
+          else tt.zo |= 1ull << b;
+        }
+        tt.ny4 = T.ny4;
+        tt.coeff = T.coeff;
+        o->tterms.push_back(tt);
+      }
+      o->tgroups.push_back(G);
+    }
+    o->sets.push_back(ps);
+  }
+}
+
 qs_obs* make_pauli_obs(int n, int nterms, const double* coeffs, const char* const* strings) {
   std::map<uint64_t, std::vector<PauliTermDev>> groups;
   for (int t = 0; t < nterms; ++t) {
@@ -487,6 +596,7 @@ qs_obs* make_pauli_obs(int n, int nterms, const double* coeffs, const char* cons
     o->goff.push_back((int)o->terms.size());
   }
   diag_poly(o);
+  pauli_sets(o);
   return o;
 }
 
@@ -989,17 +1099,14 @@ qs_status qs_adjoint(qs_circuit* c, const double* params, const qs_obs* H, qs_st
       hipck(hipMemcpyAsync(c->dparams.p, params, sizeof(double) * np, hipMemcpyHostToDevice, st), "params");
       dpar = c->dparams.as<double>();
     }
-    // lambda = H psi ; E = Re <psi|lambda>
+    // lambda = H psi and E = Re <psi|lambda> in the same passes
+    double E = 0.0;
     {
       ProfScope pr(7, st);
-      hipck(launch_apply_hamiltonian(psi->dbl(), psi->ptr, lam->ptr, psi->n, o->dflips.as<uint64_t>(),
-                                     o->dgoff.as<int>(), (int)o->flips.size(), o->dterms.as<PauliTermDev>(), st),
-            "H psi");
+      c->eout.ensure(sizeof(double));
+      pauli_pass(psi, o, lam->ptr, c->eout.as<double>());
+      hipck(hipMemcpyAsync(&E, c->eout.p, sizeof(double), hipMemcpyDeviceToHost, st), "energy");
     }
-    double* part = scratch_doubles(psi, kGridMax + 8);
-    hipck(launch_dot_re(psi->dbl(), psi->ptr, lam->ptr, psi->n, part, st), "energy");
-    double E = 0.0;
-    hipck(hipMemcpyAsync(&E, part + kGridMax, sizeof(double), hipMemcpyDeviceToHost, st), "energy");
     const int ns = c->hc.plan.ngrad_slots;
     c->gpart.ensure(sizeof(double) * (size_t(std::max(ns, 1)) * kGradStride));
     c->gout.ensure(sizeof(double) * std::max(ns, 1));

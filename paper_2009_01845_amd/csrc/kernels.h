@@ -43,6 +43,25 @@ struct PauliTermDev {
   double coeff;
 };
 
+// Pauli groups evaluated on tiles: a set holds the groups whose flip masks lie
+// in one tile bit set (the low L bits and H <= 6 high bits hbits[]).
+constexpr int kPauliMaxH = 6;
+struct PauliSet {
+  int32_t n, L, H, first;         // first: lambda is written, not accumulated
+  int32_t hbits[kPauliMaxH];
+  int32_t g0, ng;                 // groups [g0, g0 + ng) of the group array
+};
+struct PauliGroupTile {
+  uint32_t fl;                    // flip mask in tile-local bits
+  int32_t t0, nt, pad;            // terms [t0, t0 + nt) of the term array
+};
+struct PauliTermTile {
+  uint64_t zo;                    // Z/Y bits outside the tile (global positions)
+  uint32_t zl;                    // Z/Y bits inside the tile (tile-local positions)
+  int32_t ny4;                    // number of Y factors mod 4
+  double coeff;
+};
+
 // One instance of a batch: its plan lives at the given bases of the
 // concatenated pools (all offsets inside the records are instance-local).
 struct BatchInst {
@@ -94,18 +113,25 @@ hipError_t launch_set_plus(bool dbl, void* psi, int n, hipStream_t s);
 // `count` partials in a fixed order into out[0] (device).
 hipError_t launch_sumsq(bool dbl, const void* psi, int n, double* partials, hipStream_t s);
 hipError_t launch_dot_re(bool dbl, const void* a, const void* b, int n, double* partials, hipStream_t s);
-hipError_t launch_expect_group(bool dbl, const void* psi, int n, uint64_t flip, const PauliTermDev* terms,
-                               int nterms, double* partials, hipStream_t s);
+
 // One partial per workgroup of sum_x |psi_x|^2 E(x) for a diagonal observable
 // written as a quadratic polynomial in the index bits: poly = [c, mu[n],
 // lam[n*n] (upper triangle used)]; elo[j] (j < 2^min(n,12)) = the terms of
 // the low 12 bits alone, without c.
 hipError_t launch_expect_poly(bool dbl, const void* psi, int n, const double* poly, const double* elo,
                               double* partials, hipStream_t s);
-// lambda = sum_g sum_t c_t P_t psi over all groups (adjoint seed H psi)
-hipError_t launch_apply_hamiltonian(bool dbl, const void* psi, void* lam, int n, const uint64_t* flips,
-                                    const int* group_off, int ngroups, const PauliTermDev* terms,
-                                    hipStream_t s);
+// the same, also writing lambda[x] = E(x) psi[x]
+hipError_t launch_hpsi_poly(bool dbl, const void* psi, void* lam, int n, const double* poly, const double* elo,
+                            double* partials, hipStream_t s);
+// one tile set of Pauli groups: partials (one per workgroup) of sum_g Re<psi|P_g psi>;
+// with lam, also lambda (+)= sum_g P_g psi (written when set.first)
+hipError_t launch_pauli_set(bool dbl, const void* psi, void* lam, const PauliSet& set, const PauliGroupTile* groups,
+                            const PauliTermTile* terms, double* partials, hipStream_t s);
+// one group whose flip mask does not fit a tile, straight from HBM: partials of
+// Re<psi|P psi>; with lam, lambda (+)= P psi (written when first)
+hipError_t launch_pauli_far(bool dbl, const void* psi, void* lam, int n, uint64_t flip, const PauliTermDev* terms,
+                            int nterms, int first, double* partials, hipStream_t s);
+
 hipError_t launch_final_sum(const double* partials, int count, double* out, hipStream_t s);
 // out[slot] = sum of partials[slot*stride + b], b < nblocks, for every slot
 hipError_t launch_slot_sums(const double* partials, int nslots, int nblocks, int stride, double* out,

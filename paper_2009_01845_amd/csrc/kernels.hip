@@ -559,45 +559,9 @@ __device__ __forceinline__ void pauli_factor(uint64_t x, const PauliTermDev* __r
   }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_expect(const typename CT<R>::C* __restrict__ psi, int n, uint64_t flip,
-                                                const PauliTermDev* __restrict__ terms, int nt,
-                                                double* __restrict__ part) {
-  __shared__ double red[8];
-  const int64_t N = 1ll << n;
-  const int64_t units = flip ? N >> 1 : N;
-  const int hb = flip ? 63 - __builtin_clzll(flip) : 0;
-  const int64_t chunk = (units + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < units ? lo + chunk : units;
-  double acc = 0.0;
-  for (int64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) {
-    const uint64_t x = flip ? insert_zero64((uint64_t)u, hb) : (uint64_t)u;
-    double fr, fi;
-    pauli_factor(x, terms, nt, fr, fi);
-    const auto px = psi[x];
-    if (!flip) {
-      acc += ((double)px.x * px.x + (double)px.y * px.y) * fr;
-    } else {
-      const auto py = psi[x ^ flip];
-      // conj(py) * px
-      const double zr = (double)py.x * px.x + (double)py.y * px.y;
-      const double zi = (double)py.x * px.y - (double)py.y * px.x;
-      acc += 2.0 * (zr * fr - zi * fi);
-    }
-  }
-  const double r = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = r;
-}
-
-// Diagonal observable given as a quadratic polynomial in the index bits,
-// E(x) = c + sum_p mu_p x_p + sum_{p<q} lam_pq x_p x_q  (poly = [c, mu[n], lam[n*n]]).
-// Rows of 2^12 amplitudes (the low 12 bits j, the high bits h fixed):
-//   E = A(h) + Elo[j] + N1[j & 63] + N2[j >> 6],
-// Elo the pass-constant table of the low-bit terms, A the high-bit terms and
-// N1/N2 the cross terms nu_p(h) = sum_{q high, x_q = 1} lam_pq summed over
-// the set bits of each half of j.  Partials of sum |psi|^2 E per workgroup.
-template <typename R>
-__global__ __launch_bounds__(256) void k_expect_poly(const typename CT<R>::C* __restrict__ psi, int n,
+template <typename R, bool WRITE>
+__global__ __launch_bounds__(256) void k_expect_poly(const typename CT<R>::C* __restrict__ psi,
+                                                     typename CT<R>::C* __restrict__ out, int n,
                                                      const double* __restrict__ poly, const double* __restrict__ elo,
                                                      double* __restrict__ part) {
   constexpr int LB = 12;
@@ -651,32 +615,128 @@ __global__ __launch_bounds__(256) void k_expect_poly(const typename CT<R>::C* __
       const auto v = psi[hbits | (uint64_t)j];
       const double e = A + sElo[j] + N1[j & 63] + N2[j >> 6];
       acc += ((double)v.x * v.x + (double)v.y * v.y) * e;
+      if (WRITE) out[hbits | (uint64_t)j] = mk<typename CT<R>::C>(e * v.x, e * v.y);
     }
   }
   const double r = block_sum(acc, red);
   if (tid == 0) part[blockIdx.x] = r;
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_apply_ham(const typename CT<R>::C* __restrict__ psi,
-                                                   typename CT<R>::C* __restrict__ lam, int n,
-                                                   const uint64_t* __restrict__ flips,
-                                                   const int* __restrict__ goff, int ng,
-                                                   const PauliTermDev* __restrict__ terms) {
+// Pauli groups on tiles: the tile (the 2^(L+H) amplitudes sharing the bits
+// outside the set's tile bits) sits in LDS; for every element y of the tile,
+// (P_g psi)[y] = phi_g(y ^ f_g) psi[y ^ f_g] with phi_g(x) = sum_t c_t i^{ny_t}
+// (-1)^{|x & zy_t|}.  Accumulates sum_y Re(conj(psi[y]) sum_g (P_g psi)[y]) and,
+// when WRITE, adds sum_g (P_g psi)[y] to lambda (or writes it when set.first).
+template <typename R, bool WRITE>
+__global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __restrict__ psi,
+                                                    typename CT<R>::C* __restrict__ lam, const PauliSet ps,
+                                                    const PauliGroupTile* __restrict__ groups,
+                                                    const PauliTermTile* __restrict__ terms,
+                                                    double* __restrict__ part) {
   using C = typename CT<R>::C;
-  const int64_t N = 1ll << n;
-  for (int64_t y = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; y < N; y += (int64_t)gridDim.x * blockDim.x) {
-    double ar = 0.0, ai = 0.0;
-    for (int gi = 0; gi < ng; ++gi) {
-      const uint64_t x = (uint64_t)y ^ flips[gi];
-      double fr, fi;
-      pauli_factor(x, terms + goff[gi], goff[gi + 1] - goff[gi], fr, fi);
-      const C v = psi[x];
-      ar += fr * v.x - fi * v.y;
-      ai += fr * v.y + fi * v.x;
-    }
-    lam[y] = mk<C>(ar, ai);
+  constexpr int EPT = 16;  // elements per thread: tiles hold at most 2^12 = 16 * 256 amplitudes
+  extern __shared__ __align__(16) char smem[];
+  C* tile = reinterpret_cast<C*>(smem);
+  __shared__ uint64_t hoff[1 << kPauliMaxH];
+  __shared__ int hb[kPauliMaxH];
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  const int L = ps.L, H = ps.H, m = L + H;
+  const int M = 1 << m;
+  const int64_t ntiles = 1ll << (ps.n - m);
+  const uint32_t lomask = (1u << L) - 1u;
+  if (tid < kPauliMaxH) hb[tid] = ps.hbits[tid];
+  for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
+    uint64_t off = 0;
+    for (int i = 0; i < H; ++i)
+      if ((hc >> i) & 1) off |= 1ull << ps.hbits[i];
+    hoff[hc] = off;
   }
+  __syncthreads();
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint64_t base = (uint64_t)t << L;
+    for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
+    for (int j = tid; j < M; j += blockDim.x) tile[j] = psi[base | hoff[j >> L] | (uint64_t)(j & lomask)];
+    __syncthreads();
+    R ar[EPT], ai[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) ar[e] = ai[e] = (R)0;
+    for (int gi = 0; gi < ps.ng; ++gi) {  // uniform: one term at a time over all elements
+      const PauliGroupTile G = groups[ps.g0 + gi];
+      for (int ti = 0; ti < G.nt; ++ti) {
+        const PauliTermTile T = terms[G.t0 + ti];
+        // c i^ny (-1)^{|base & zo|} as a complex coefficient (kr, ki)
+        const double c = (__popcll(base & T.zo) & 1) ? -T.coeff : T.coeff;
+        const R kr = (R)(T.ny4 == 0 ? c : T.ny4 == 2 ? -c : 0.0);
+        const R ki = (R)(T.ny4 == 1 ? c : T.ny4 == 3 ? -c : 0.0);
+        const uint32_t zl = T.zl;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int y = tid + e * (int)blockDim.x;
+          if (y < M) {
+            const uint32_t x = (uint32_t)y ^ G.fl;
+            const C px = tile[x];
+            const bool neg = (__popc(x & zl) & 1) != 0;
+            const R sr = neg ? -kr : kr, si = neg ? -ki : ki;
+            ar[e] += sr * px.x - si * px.y;
+            ai[e] += sr * px.y + si * px.x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int y = tid + e * (int)blockDim.x;
+      if (y < M) {
+        const C py = tile[y];
+        acc += (double)py.x * ar[e] + (double)py.y * ai[e];
+        if (WRITE) {
+          const uint64_t ga = base | hoff[y >> L] | (uint64_t)(y & lomask);
+          if (ps.first) {
+            lam[ga] = mk<C>(ar[e], ai[e]);
+          } else {
+            const C l = lam[ga];
+            lam[ga] = mk<C>((double)l.x + ar[e], (double)l.y + ai[e]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const double r = block_sum(acc, red);
+  if (tid == 0) part[blockIdx.x] = r;
+}
+
+// one Pauli group with a flip mask spread over many high bits: every thread
+// gathers psi[y ^ flip] for its outputs y straight from HBM
+template <typename R, bool WRITE>
+__global__ __launch_bounds__(256) void k_pauli_far(const typename CT<R>::C* __restrict__ psi,
+                                                   typename CT<R>::C* __restrict__ lam, int n, uint64_t flip,
+                                                   const PauliTermDev* __restrict__ terms, int nt, int first,
+                                                   double* __restrict__ part) {
+  using C = typename CT<R>::C;
+  __shared__ double red[8];
+  const int64_t N = 1ll << n;
+  double acc = 0.0;
+  for (int64_t y = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; y < N; y += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = (uint64_t)y ^ flip;
+    double fr, fi;
+    pauli_factor(x, terms, nt, fr, fi);
+    const C px = psi[x], py = psi[y];
+    const double ar = fr * px.x - fi * px.y, ai = fr * px.y + fi * px.x;
+    acc += (double)py.x * ar + (double)py.y * ai;
+    if (WRITE) {
+      if (first) {
+        lam[y] = mk<C>(ar, ai);
+      } else {
+        const C l = lam[y];
+        lam[y] = mk<C>((double)l.x + ar, (double)l.y + ai);
+      }
+    }
+  }
+  const double r = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
 __global__ __launch_bounds__(256) void k_final_sum(const double* __restrict__ part, int count, double* out) {
@@ -2149,45 +2209,85 @@ hipError_t launch_dot_re(bool dbl, const void* a, const void* b, int n, double* 
   return launch_final_sum(partials, grid, partials + kGridMax, s);
 }
 
-hipError_t launch_expect_group(bool dbl, const void* psi, int n, uint64_t flip, const PauliTermDev* terms,
-                               int nterms, double* partials, hipStream_t s) {
-  const int64_t units = flip ? (1ll << (n - 1)) : (1ll << n);
-  const int grid = reduce_grid(units);
-  if (dbl)
-    hipLaunchKernelGGL((k_expect<double>), dim3(grid), dim3(256), 0, s, (const double2*)psi, n, flip, terms,
-                       nterms, partials);
-  else
-    hipLaunchKernelGGL((k_expect<float>), dim3(grid), dim3(256), 0, s, (const float2*)psi, n, flip, terms, nterms,
-                       partials);
-  return hipGetLastError();
-}
-
-hipError_t launch_expect_poly(bool dbl, const void* psi, int n, const double* poly, const double* elo,
-                              double* partials, hipStream_t s) {
+template <bool WRITE>
+hipError_t expect_poly_t(bool dbl, const void* psi, void* lam, int n, const double* poly, const double* elo,
+                         double* partials, hipStream_t s) {
   if (n < 1 || n > kMaxQubits) return hipErrorInvalidValue;
   const int lb = n < 12 ? n : 12;
   const int64_t nt = 1ll << (n - lb);
   const int grid = (int)(nt < kGridMax ? nt : kGridMax);
   if (dbl)
-    hipLaunchKernelGGL((k_expect_poly<double>), dim3(grid), dim3(256), 0, s, (const double2*)psi, n, poly, elo,
-                       partials);
+    hipLaunchKernelGGL((k_expect_poly<double, WRITE>), dim3(grid), dim3(256), 0, s, (const double2*)psi,
+                       (double2*)lam, n, poly, elo, partials);
   else
-    hipLaunchKernelGGL((k_expect_poly<float>), dim3(grid), dim3(256), 0, s, (const float2*)psi, n, poly, elo,
-                       partials);
+    hipLaunchKernelGGL((k_expect_poly<float, WRITE>), dim3(grid), dim3(256), 0, s, (const float2*)psi,
+                       (float2*)lam, n, poly, elo, partials);
   return hipGetLastError();
 }
 
-hipError_t launch_apply_hamiltonian(bool dbl, const void* psi, void* lam, int n, const uint64_t* flips,
-                                    const int* group_off, int ngroups, const PauliTermDev* terms,
-                                    hipStream_t s) {
-  const int64_t N = 1ll << n;
-  const int grid = (int)std::min<int64_t>((N + 255) / 256, 8192);
-  if (dbl)
-    hipLaunchKernelGGL((k_apply_ham<double>), dim3(grid), dim3(256), 0, s, (const double2*)psi, (double2*)lam, n,
-                       flips, group_off, ngroups, terms);
-  else
-    hipLaunchKernelGGL((k_apply_ham<float>), dim3(grid), dim3(256), 0, s, (const float2*)psi, (float2*)lam, n,
-                       flips, group_off, ngroups, terms);
+hipError_t launch_expect_poly(bool dbl, const void* psi, int n, const double* poly, const double* elo,
+                              double* partials, hipStream_t s) {
+  return expect_poly_t<false>(dbl, psi, nullptr, n, poly, elo, partials, s);
+}
+
+hipError_t launch_hpsi_poly(bool dbl, const void* psi, void* lam, int n, const double* poly, const double* elo,
+                            double* partials, hipStream_t s) {
+  if (!lam) return hipErrorInvalidValue;
+  return expect_poly_t<true>(dbl, psi, lam, n, poly, elo, partials, s);
+}
+
+hipError_t launch_pauli_far(bool dbl, const void* psi, void* lam, int n, uint64_t flip, const PauliTermDev* terms,
+                            int nterms, int first, double* partials, hipStream_t s) {
+  if (n < 1 || n > kMaxQubits || (flip >> n) != 0) return hipErrorInvalidValue;
+  const int grid = reduce_grid(1ll << n);
+  if (dbl) {
+    if (lam)
+      hipLaunchKernelGGL((k_pauli_far<double, true>), dim3(grid), dim3(256), 0, s, (const double2*)psi, (double2*)lam,
+                         n, flip, terms, nterms, first, partials);
+    else
+      hipLaunchKernelGGL((k_pauli_far<double, false>), dim3(grid), dim3(256), 0, s, (const double2*)psi, nullptr, n,
+                         flip, terms, nterms, first, partials);
+  } else {
+    if (lam)
+      hipLaunchKernelGGL((k_pauli_far<float, true>), dim3(grid), dim3(256), 0, s, (const float2*)psi, (float2*)lam, n,
+                         flip, terms, nterms, first, partials);
+    else
+      hipLaunchKernelGGL((k_pauli_far<float, false>), dim3(grid), dim3(256), 0, s, (const float2*)psi, nullptr, n,
+                         flip, terms, nterms, first, partials);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pauli_set(bool dbl, const void* psi, void* lam, const PauliSet& set, const PauliGroupTile* groups,
+                            const PauliTermTile* terms, double* partials, hipStream_t s) {
+  const int m = set.L + set.H;
+  if (set.n < 1 || set.n > kMaxQubits || set.L < 0 || set.H < 0 || set.H > kPauliMaxH || m > 12 || m > set.n)
+    return hipErrorInvalidValue;
+  for (int i = 0; i < set.H; ++i)
+    if (set.hbits[i] < set.L || set.hbits[i] >= set.n || (i && set.hbits[i] <= set.hbits[i - 1]))
+      return hipErrorInvalidValue;
+  const int64_t nt = 1ll << (set.n - m);
+  const int grid = (int)(nt < kGridMax ? nt : kGridMax);
+  const size_t lds = (size_t(1) << m) * (dbl ? 16 : 8);
+  if (dbl) {
+    hipError_t e = set_lds_fn(lam ? (void*)k_pauli_tile<double, true> : (void*)k_pauli_tile<double, false>, lds);
+    if (e != hipSuccess) return e;
+    if (lam)
+      hipLaunchKernelGGL((k_pauli_tile<double, true>), dim3(grid), dim3(256), lds, s, (const double2*)psi,
+                         (double2*)lam, set, groups, terms, partials);
+    else
+      hipLaunchKernelGGL((k_pauli_tile<double, false>), dim3(grid), dim3(256), lds, s, (const double2*)psi, nullptr,
+                         set, groups, terms, partials);
+  } else {
+    hipError_t e = set_lds_fn(lam ? (void*)k_pauli_tile<float, true> : (void*)k_pauli_tile<float, false>, lds);
+    if (e != hipSuccess) return e;
+    if (lam)
+      hipLaunchKernelGGL((k_pauli_tile<float, true>), dim3(grid), dim3(256), lds, s, (const float2*)psi,
+                         (float2*)lam, set, groups, terms, partials);
+    else
+      hipLaunchKernelGGL((k_pauli_tile<float, false>), dim3(grid), dim3(256), lds, s, (const float2*)psi, nullptr,
+                         set, groups, terms, partials);
+  }
   return hipGetLastError();
 }
 

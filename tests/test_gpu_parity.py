@@ -221,6 +221,41 @@ def test_diagonal_polynomial_expectation(api, dt, n):
         assert abs(H.expectation(st) - oobs.expectation(ref, terms).real) < tol * n
 
 
+@pytest.mark.parametrize("dt", DTS)
+def test_pauli_tile_sets_expectation_and_adjoint(api, dt):
+    # flip masks spread over every bit (several tile sets), Y factors, a
+    # diagonal group with a three-Z term (no polynomial form), and an
+    # observable with only off-diagonal groups (the first set writes lambda)
+    n = 16
+    banner("pauli sets", dt)
+    rng = np.random.default_rng(17)
+    psi0 = qsynth.random_state(n, 23)
+    st = gpu_state(api, n, dt, psi0)
+    ref = oracle_input(psi0, dt)
+    tol = 1e-11 if dt == "c128" else 2e-6
+    mixed = [(float(rng.normal()), qsynth.pauli_string(n, {int(q): "XYZ"[int(rng.integers(3))]
+                                                          for q in rng.choice(n, int(rng.integers(1, 4)), replace=False)}))
+             for _ in range(40)]
+    mixed.append((0.3, qsynth.pauli_string(n, {1: "Z", 5: "Z", 12: "Z"})))
+    # flips on more high bits than a tile holds: the direct per-group path
+    mixed.append((0.45, qsynth.pauli_string(n, {q: "XY"[q % 2] for q in range(9)})))
+    mixed.append((-0.2, qsynth.pauli_string(n, {q: "X" for q in range(0, 16, 2)})))
+    only_x = [(0.5 + 0.1 * q, qsynth.pauli_string(n, {q: "X"})) for q in range(n)]
+    for terms in (mixed, only_x):
+        H = api.Observable.pauli_sum(n, terms)
+        assert abs(H.expectation(st) - oobs.expectation(ref, terms).real) < tol * 10
+    if dt == "c128":
+        _, spec, params, _ = qsynth.gradient_20q(seed=3, n=n, layers=2)
+        c = api.Circuit.from_spec(n, spec)
+        for terms in (mixed, only_x):
+            psi, lam = api.State(n, dt), api.State(n, dt)
+            c.run(psi, params)
+            H = api.Observable.pauli_sum(n, terms)
+            e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+            e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+            assert abs(e - e_ref) < 1e-10 and np.max(np.abs(g - g_ref)) < 1e-10
+
+
 # ---------------------------------------------------------------- sampling
 @pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("shots", [1, 7, 4099])
