@@ -101,6 +101,87 @@ def dense_blocks(n: int, seed: int = 11):
     return [qsynth.gate("MAT", t, mat=qsynth.haar_unitary(1 << len(t), rng)) for t in sets]
 
 
+def sweep(n: int, dt: str, only: str | None):
+    """Per-kernel-kind table at n qubits: one JSON line per case with the
+    device time per launch (HIP events on the launch stream), algorithmic
+    GB/s and its fraction of 8 TB/s and of a device copy measured alongside;
+    matrix-core blocks also report TFLOP/s."""
+    import numpy as np
+    import torch
+
+    import qsynth
+    from paper_2009_01845_amd import api
+    rng = np.random.default_rng(0)
+    b = 8 if dt == "c64" else 16
+    bytes_pass = 2 * (1 << n) * b
+    st = api.State(n, dt)
+    st.set_plus()
+    y = torch.empty_like(st.tensor)
+    for _ in range(2):
+        y.copy_(st.tensor)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        y.copy_(st.tensor)
+    torch.cuda.synchronize()
+    copy_gbs = bytes_pass / ((time.perf_counter() - t) / 5) / 1e9
+    del y
+    torch.cuda.empty_cache()
+    print(json.dumps({"case": "device_copy", "GB/s": copy_gbs}), flush=True)
+    Q = lambda bit: n - 1 - bit  # noqa: E731  (qubit holding index bit `bit`)
+    hu = lambda k: qsynth.haar_unitary(1 << k, rng)  # noqa: E731
+    cases = {}
+    for bit in (0, 5, 6, 11, 12, 20, n - 1):
+        cases[f"haar1q_bit{bit}"] = [qsynth.gate("MAT", (Q(bit),), mat=hu(1))]
+    cases["H_bit17"] = [qsynth.gate("H", (Q(17),))]
+    cases["X_bit17"] = [qsynth.gate("X", (Q(17),))]
+    cases["RZ_bit17"] = [qsynth.gate("RZ", (Q(17),), theta=0.3)]
+    cases["Z_bit17"] = [qsynth.gate("Z", (Q(17),))]
+    cases["CZ_chain"] = [qsynth.gate("Z", (q + 1,), (q,)) for q in range(n - 1)]
+    cases["CRY_bits3_20"] = [qsynth.gate("RY", (Q(3),), (Q(20),), theta=0.7)]
+    cases["haar2q_bits9_10"] = [qsynth.gate("MAT", (Q(10), Q(9)), mat=hu(2))]
+    cases["haar2q_bits4_25"] = [qsynth.gate("MAT", (Q(4), Q(n - 5)), mat=hu(2))]
+    for g in (2, 4, 8, 12):
+        bits = [0, 1, 2, 3, 4, 5, n - 1, n - 2, n - 3, n - 4, n - 5, n - 6][:g]
+        cases[f"pass_{g}_haar1q"] = [qsynth.gate("MAT", (Q(bt),), mat=hu(1)) for bt in bits]
+    cases["swap_network"] = [qsynth.gate("SWAP", (j, n - 1 - j)) for j in range(n // 2)]
+    mf = {}
+    for k, tg in ((3, (0, 1, 2)), (4, (0, 1, 2, 3)), (5, (0, 1, 2, 3, 4)), (4, (n - 4, n - 3, n - 2, n - 1)),
+                  (5, (0, n // 4, n // 2, 3 * n // 4, n - 1))):
+        name = f"mfma_k{k}_q" + "_".join(map(str, tg))
+        cases[name] = [qsynth.gate("MAT", tg, mat=hu(k))]
+        mf[name] = k
+    fam = {1: 0, 3: 2, 4: 3}
+    for name, spec in cases.items():
+        if only and only not in name:
+            continue
+        c = api.Circuit.from_spec(n, spec, use_mfma=1 if name in mf else -1)
+        kinds = [k for k, _, _ in c.passes()]
+        for _ in range(2):
+            c.run(st)
+        torch.cuda.synchronize()
+        api.profile_reset()
+        api.profile_enable(True)
+        reps = 4
+        for _ in range(reps):
+            c.run(st)
+        torch.cuda.synchronize()
+        api.profile_enable(False)
+        ms, launches = 0.0, 0
+        for f in set(fam.get(k, 0) for k in kinds):
+            cnt, tot = api.profile_read(f)
+            ms += tot
+            launches += cnt
+        per = ms / max(launches, 1)
+        gbs = bytes_pass / (per / 1e3) / 1e9
+        row = {"case": name, "dtype": dt, "passes": len(kinds), "ms_per_pass": per, "GB/s": gbs,
+               "frac_of_8TBs": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs}
+        if name in mf:
+            k = mf[name]
+            row["TFLOP/s"] = 8 * (1 << k) * (1 << n) / (per / 1e3) / 1e12
+        print(json.dumps(row), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,9 +193,15 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick each 30-qubit circuit's plan by timing first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="per-kernel-kind table instead of the step (one line per case)")
+    ap.add_argument("--sweep-dtype", default="c64")
+    ap.add_argument("--sweep-only", default=None, help="run the sweep cases whose name contains this text")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         sys.exit("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)")
+    if args.sweep:
+        sweep(args.n, args.sweep_dtype, args.sweep_only)
+        return
 
     import numpy as np
     import torch

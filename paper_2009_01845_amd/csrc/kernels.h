@@ -100,7 +100,7 @@ hipError_t launch_rot_mats(bool dbl, const DevPlan& dp, const double* params, hi
 // exp(i scale * angle) factors of every scaled phase record (scales[rec.scale_idx])
 hipError_t launch_phase_tabs(bool dbl, const DevPlan& dp, const double* scales, hipStream_t s);
 hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* tau, hipStream_t s);
-// Dense k-qubit block (k = 3..5) with matrix-core instructions; the tile is the
+// Dense k-qubit block (k = 4, 5) with matrix-core instructions; the tile is the
 // targets plus the 7 lowest other bits (g.m == k + 7); tl[t] = tile-local
 // position of target t; mat = 2^k x 2^k complex128 (device).
 hipError_t launch_mfma_pass(bool dbl, void* psi, const PassGeom& g, const int* tl, int k, const double* mat,

@@ -1660,7 +1660,7 @@ __global__ __launch_bounds__(256) void k_tile2(
 }
 
 // ----------------------------------------------------------------------------
-// dense k-qubit block (k = 3..5) on matrix cores.  A tile holds the 2^k target
+// dense k-qubit block (k = 4, 5) on matrix cores.  A tile holds the 2^k target
 // values of 128 columns (the 7 lowest non-target bits); with the gate realified
 // as GR = [[Gr, -Gi], [Gi, Gr]] (2^(k+1) square) every column is updated by one
 // real product [Yr; Yi] = GR [Xr; Xi].  v_mfma_*_16x16x4: A is 16x4 (lane l
@@ -2103,7 +2103,7 @@ hipError_t mfma_launch_t(void* psi, const PassGeom& g, const MfmaArgs& ma, const
 hipError_t launch_mfma_pass(bool dbl, void* psi, const PassGeom& g, const int* tl, int k, const double* mat,
                             hipStream_t s) {
   // tile = targets + 7 other bits: L may reach 12 when the targets are low bits
-  if (k < 3 || k > 5 || g.m != k + 7 || g.m > g.n || g.n > kMaxQubits) return hipErrorInvalidValue;
+  if (k < 4 || k > 5 || g.m != k + 7 || g.m > g.n || g.n > kMaxQubits) return hipErrorInvalidValue;
   if (g.L < 7 || g.L > 12 || g.H < 0 || g.H > 5 || g.L + g.H != g.m) return hipErrorInvalidValue;
   for (int i = 0; i < g.H; ++i)
     if (g.hbits[i] < g.L || g.hbits[i] >= g.n || (i && g.hbits[i] <= g.hbits[i - 1])) return hipErrorInvalidValue;
@@ -2116,11 +2116,9 @@ hipError_t launch_mfma_pass(bool dbl, void* psi, const PassGeom& g, const int* t
     ma.tl[t] = tl[t];
   }
   if (dbl) {
-    if (k == 3) return mfma_launch_t<double, 3>(psi, g, ma, mat, s);
     if (k == 4) return mfma_launch_t<double, 4>(psi, g, ma, mat, s);
     return mfma_launch_t<double, 5>(psi, g, ma, mat, s);
   }
-  if (k == 3) return mfma_launch_t<float, 3>(psi, g, ma, mat, s);
   if (k == 4) return mfma_launch_t<float, 4>(psi, g, ma, mat, s);
   return mfma_launch_t<float, 5>(psi, g, ma, mat, s);
 }

@@ -192,7 +192,7 @@ BitGate to_bits(const Gate& g, int n, const std::vector<int>& phys, const TuneOp
     b.nmask = tmask;
     const int kt = g.k + (int)g.cq.size();
     const int kmin = opts.use_mfma > 0 ? 3 : 4;
-    if (opts.use_mfma != 0 && kt >= kmin && kt <= 5 && n >= kt + 7) {
+    if (opts.use_mfma != 0 && kt >= kmin && kt <= 5 && n >= std::max(kt, 4) + 7) {
       // the whole controlled gate becomes one dense block on matrix cores
       b.mfma = true;
       if (!g.cq.empty()) {
@@ -204,6 +204,21 @@ BitGate to_bits(const Gate& g, int n, const std::vector<int>& phys, const TuneOp
         b.nmask = b.cmask | tmask;
         b.dmask = 0;
         b.cmask = 0;
+      }
+      if (b.k == 3) {
+        // the matrix-core kernel takes 4- and 5-qubit blocks: widen to G (x) I
+        // with the lowest free index bit as the new least significant target
+        uint64_t used = 0;
+        for (int t = 0; t < 3; ++t) used |= 1ull << b.tb[t];
+        const int e = __builtin_ctzll(~used);
+        std::vector<cd> M(256, cd(0, 0));
+        for (int r = 0; r < 8; ++r)
+          for (int c = 0; c < 8; ++c)
+            for (int a = 0; a < 2; ++a) M[size_t((r << 1) | a) * 16 + ((c << 1) | a)] = b.mat[size_t(r) * 8 + c];
+        b.mat = M;
+        b.tb[3] = e;
+        b.k = 4;
+        b.nmask |= 1ull << e;
       }
     }
     return b;

@@ -160,3 +160,14 @@ def test_dense_blocks_plan_onto_matrix_cores(api):
     assert [k for k, _, _ in on.passes()].count(4) == 2
     assert [k for k, _, _ in auto.passes()].count(4) == 2   # k + controls >= 4 by default
     assert 4 not in [k for k, _, _ in off.passes()]
+
+
+def test_three_qubit_blocks_widen_for_matrix_cores(api):
+    rng = np.random.default_rng(2)
+    spec = [qsynth.gate("MAT", (3, 8, 11), mat=qsynth.haar_unitary(8, rng))]
+    on = api.Circuit.from_spec(14, spec, use_mfma=1)
+    assert [k for k, _, _ in on.passes()] == [4]
+    assert on.passes()[0][1] == 11          # tile = 4 widened targets + 7 other bits
+    spec10 = [qsynth.gate("MAT", (3, 8, 9), mat=qsynth.haar_unitary(8, rng))]
+    small = api.Circuit.from_spec(10, spec10, use_mfma=1)   # 4 + 7 > 10: no matrix cores
+    assert 4 not in [k for k, _, _ in small.passes()]

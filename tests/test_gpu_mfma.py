@@ -47,6 +47,20 @@ def test_mfma_blocks_vs_oracle(api, dt, n):
     assert maxabs(st.download(), ref) < TOL[dt]
 
 
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_mfma_uncontrolled_three_qubit_blocks(api, dt):
+    # 3-qubit blocks are widened to 4 (G x I on a free bit) for matrix cores
+    n = 13
+    banner("mfma k3", dt)
+    spec = blocks(n, 41, ks=(3,), count=5, ctrl=False)
+    c = api.Circuit.from_spec(n, spec, use_mfma=1)
+    assert [k for k, _, _ in c.passes()].count(4) == 5
+    psi0 = qsynth.random_state(n, 3)
+    st = gpu_state(api, n, dt, psi0)
+    c.run(st)
+    assert maxabs(st.download(), ocirc.run(n, spec, oracle_input(psi0, dt))) < TOL[dt]
+
+
 def test_mfma_low_and_high_targets(api):
     n = 14
     banner("mfma targets")
