@@ -1244,11 +1244,8 @@ struct PassSmem {
   double phCk[kMaxPhasePerPass][kMaxKBits];
   int hb[kMaxTileBits];
   int kpos[kMaxKBits];
-  double gacc[kMaxGradPerPass][kThreads / 64];  // adjoint partials of this pass, per wave
-  // exp(i phNu[p][b]) for the tile bits b and exp(i phA[p]) at b = kMaxTileBits,
-  // stored in the state precision in the first half of each slot
-  double2 en[kMaxPhasePerPass][kMaxTileBits + 1];
 };
+constexpr int kEnRow = kMaxTileBits + 1;  // exp(i phNu[p][b]) for tile bits b, exp(i phA[p]) at b = kMaxTileBits
 
 // One staged pass over tiles t_first, t_first + t_step, ... < ntiles; the
 // tile-index bits above gbits are the "k bits" of the phase tables.  GUARD:
@@ -1265,7 +1262,8 @@ __device__ __forceinline__ void pass_body(
     const typename CT<R>::C* __restrict__ qtab, const double* __restrict__ qang,
     const double* __restrict__ scales, const typename CT<R>::C* __restrict__ ctab, double* __restrict__ gpart,
     int64_t gstride, int gcol,
-    int64_t t_first, int64_t t_step, int64_t ntiles, int gbits, PassSmem& sm, char* smem) {
+    int64_t t_first, int64_t t_step, int64_t ntiles, int gbits, PassSmem& sm, char* smem,
+    typename CT<R>::C* __restrict__ en, double* __restrict__ gacc) {
   using C = typename CT<R>::C;
   using VT = typename CT<R>::V;
   constexpr int VW = CT<R>::VW;
@@ -1287,7 +1285,7 @@ __device__ __forceinline__ void pass_body(
   const int kb = (n - m) - gbits;
   if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
   if (TWO)
-    for (int i = tid; i < kMaxGradPerPass * (kThreads / 64); i += blockDim.x) (&sm.gacc[0][0])[i] = 0.0;
+    for (int i = tid; i < kMaxGradPerPass * (kThreads / 64); i += blockDim.x) gacc[i] = 0.0;
   if (tid == 0) {  // global positions of the tile-index bits above the grid
     int idx = 0;
     uint64_t tm = (1ull << L) - 1;
@@ -1380,7 +1378,7 @@ __device__ __forceinline__ void pass_body(
             if ((kk >> j) & 1) s += kt[b * kMaxKBits + j];
           const double a = phNu0[p][b] + scl * s;
           phNu[p][b] = a;
-          *reinterpret_cast<C*>(&sm.en[p][b]) = expi<C>(a);
+          en[p * kEnRow + b] = expi<C>(a);
         } else if (b == 15) {
           double s = phA0[p];
 #pragma unroll
@@ -1388,7 +1386,7 @@ __device__ __forceinline__ void pass_body(
             if ((kk >> j) & 1) s += phCk[p][j];
           const double a = s + scl * kt[m * kMaxKBits + kk];
           phA[p] = a;
-          *reinterpret_cast<C*>(&sm.en[p][kMaxTileBits]) = expi<C>(a);
+          en[p * kEnRow + kMaxTileBits] = expi<C>(a);
         }
       }
       __syncthreads();
@@ -1463,7 +1461,7 @@ __device__ __forceinline__ void pass_body(
           const PhaseRec rec = phases[op.aux];
           const C* bc = ctab + rec.ctab_off + grp * (NR + 1);
           const C* wc = ctab + rec.ctab_off + (rec.ctab_n - NE);
-          auto EN = [&](int b) { return *reinterpret_cast<const C*>(&sm.en[p][b]); };
+          auto EN = [&](int b) { return en[p * kEnRow + b]; };
           auto B = [&](int k) { return TWO ? cconj(bc[k]) : bc[k]; };
           const bool wtriv = rec.wr_trivial != 0;
           C f = cmul(EN(kMaxTileBits), B(0));
@@ -1504,7 +1502,7 @@ __device__ __forceinline__ void pass_body(
           const C* bc = ctab + rec.ctab_off + grp * (NR + 1);
           const C* wc = ctab + rec.ctab_off + (rec.ctab_n - NE);
           const C b = TWO ? cconj(bc[1 + KBS]) : bc[1 + KBS];
-          const C F = cmul(*reinterpret_cast<const C*>(&sm.en[p][sr.rb[KBS]]), b);
+          const C F = cmul(en[p * kEnRow + sr.rb[KBS]], b);
           const bool wtriv = rec.wr_trivial != 0;
 #pragma unroll
           for (int e = 0; e < NE; ++e) {
@@ -1533,7 +1531,7 @@ __device__ __forceinline__ void pass_body(
             }
             if (!uact) pg = 0;
             pg = wave_sum_rows(row_sum(pg));
-            if ((tid & 63) == 63) sm.gacc[ops[o].aux][tid >> 6] += (double)pg;
+            if ((tid & 63) == 63) gacc[ops[o].aux * (kThreads / 64) + (tid >> 6)] += (double)pg;
           }
           if (!uact) continue;
           if (cin == 0 && creg == 0) {
@@ -1637,7 +1635,8 @@ __device__ __forceinline__ void pass_body(
     for (int i = tid; i < g.nops * (kThreads / 64); i += blockDim.x) {
       const int oi = i / (kThreads / 64), w = i % (kThreads / 64);
       const TileOp& op = ops[op0 + oi];
-      if (op.kind == OP_ROT && op.gslot >= 0) gpart[(int64_t)op.gslot * gstride + gcol + w] = sm.gacc[op.aux][w];
+      if (op.kind == OP_ROT && op.gslot >= 0)
+        gpart[(int64_t)op.gslot * gstride + gcol + w] = gacc[op.aux * (kThreads / 64) + w];
     }
     __syncthreads();  // a following pass in the same workgroup reuses gacc
   }
@@ -1654,9 +1653,11 @@ __global__ __launch_bounds__(256) void k_tile2(
     int64_t ntiles) {
   extern __shared__ __align__(16) char smem[];
   __shared__ PassSmem sm;
+  __shared__ typename CT<R>::C en[kMaxPhasePerPass * kEnRow];
+  __shared__ double gacc[TWO ? kMaxGradPerPass * (kThreads / 64) : 1];
   pass_body<R, TWO, NLD, false, CTRL>(psi, lam, g, ops, stages, matc, phases, phlist, dpool, btab, qtab, qang, scales,
                                 ctab, gpart, kGradStride, blockIdx.x * 4, blockIdx.x, gridDim.x, ntiles,
-                                __builtin_ctz(gridDim.x), sm, smem);
+                                __builtin_ctz(gridDim.x), sm, smem, en, gacc);
 }
 
 // ----------------------------------------------------------------------------
@@ -1821,6 +1822,8 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) char smem[];
   __shared__ PassSmem sm;
+  __shared__ C en[kMaxPhasePerPass * kEnRow];
+  __shared__ double gacc[kMaxGradPerPass * (kThreads / 64)];
   __shared__ int cur;
   __shared__ double red[8];
   const int tid = threadIdx.x;
@@ -1872,13 +1875,13 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
                                          matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
                                          a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
                                          a.dp.qang + in.qt_base, nullptr, ctab + in.ct_base, gp, 4, 0, 0, 1, nt,
-                                         0, sm, smem);
+                                         0, sm, smem, en, gacc);
         else
           pass_body<R, true, NLD, true, true>(psi, lam, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
                                         matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
                                         a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
                                         a.dp.qang + in.qt_base, nullptr, ctab + in.ct_base, gp, 4, 0, 0, 1, nt, 0,
-                                        sm, smem);
+                                        sm, smem, en, gacc);
       }
     }
     // gradient of every parameter, slots in order (deterministic)

@@ -45,7 +45,7 @@ struct TileOp {
 };
 
 constexpr int kRegBits = 4;            // register slots per thread in a staged pass
-constexpr int kMaxPhasePerPass = 16;   // phase ops whose tile terms are prepared per tile
+constexpr int kMaxPhasePerPass = 14;   // phase ops whose tile terms are prepared per tile
 constexpr int kMaxGradPerPass = 64;    // parameterised rotations per pass (adjoint partials kept in LDS)
 constexpr int kGridBits = 11;          // streaming grids hold at most 2^kGridBits workgroups
 constexpr int kMaxKBits = 12;          // tile-index bits above the grid: n - m - kGridBits <= 12
