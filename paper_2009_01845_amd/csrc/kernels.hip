@@ -4,6 +4,11 @@
 // index bit n-1-q.  Every streaming kernel is bound by HBM bandwidth: it reads
 // and writes each amplitude once per pass with 16-byte vector accesses, and
 // the index arithmetic is 64-bit throughout (2^35 amplitudes).
+//
+// Every kernel with a thread loop is launched with kThreads threads and uses
+// that constant for its stride: on gfx950 blockDim.x is a vector load from the
+// implicit arguments, and each reload waits on all of the wave's outstanding
+// vector memory operations (prefetches included).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -21,11 +26,13 @@ template <typename R> struct CT;
 template <> struct CT<float> {
   using C = float2;
   using V = float4;  // 16-byte access = 2 amplitudes
+  typedef float NV __attribute__((ext_vector_type(4)));
   static constexpr int VW = 2;
 };
 template <> struct CT<double> {
   using C = double2;
   using V = double2;  // 16-byte access = 1 amplitude
+  typedef double NV __attribute__((ext_vector_type(2)));
   static constexpr int VW = 1;
 };
 
@@ -85,7 +92,7 @@ __device__ double block_sum(double v, double* red) {
   __syncthreads();
   double r = 0.0;
   if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += red[i];
+    for (int i = 0; i < (int)(kThreads >> 6); ++i) r += red[i];
   __syncthreads();
   return r;
 }
@@ -110,7 +117,7 @@ __device__ void op_dense1(C* t1, C* t2, int M, int b, uint32_t cin, C m00, C m01
   const uint32_t B = 1u << b;
   const uint32_t mask = B | cin;
   const int np = (M >> 1) >> __popc(cin);
-  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+  for (int i = threadIdx.x; i < np; i += kThreads) {
     const uint32_t j = insert_zeros((uint32_t)i, mask) | cin;
     pair2(t1, j, j | B, m00, m01, m10, m11);
     if (TWO) pair2(t2, j, j | B, m00, m01, m10, m11);
@@ -143,7 +150,7 @@ __device__ void op_dense2(C* t1, C* t2, int M, const TileOp& op, const double* m
   const uint32_t B0 = 1u << op.b[0], B1 = 1u << op.b[1];
   const uint32_t mask = B0 | B1 | op.cin;
   const int nq = (M >> 2) >> __popc(op.cin);
-  for (int i = threadIdx.x; i < nq; i += blockDim.x) {
+  for (int i = threadIdx.x; i < nq; i += kThreads) {
     const uint32_t j = insert_zeros((uint32_t)i, mask) | op.cin;
     quad4(t1, j, B0, B1, mm);
     if (TWO) quad4(t2, j, B0, B1, mm);
@@ -182,7 +189,7 @@ __device__ void op_densek(C* t1, C* t2, int M, const TileOp& op, const double* m
   }
   const uint32_t mask = tmask | op.cin;
   const int ng = (M >> K) >> __popc(op.cin);
-  for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+  for (int i = threadIdx.x; i < ng; i += kThreads) {
     const uint32_t j0 = insert_zeros((uint32_t)i, mask) | op.cin;
     groupk<K>(t1, j0, offs, mp);
     if (TWO) groupk<K>(t2, j0, offs, mp);
@@ -196,7 +203,7 @@ __device__ double rot_grad_partial(const C* ps, const C* la, int M, int b, uint3
   const uint32_t mask = B | cin;
   const int np = (M >> 1) >> __popc(cin);
   double acc = 0.0;
-  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+  for (int i = threadIdx.x; i < np; i += kThreads) {
     const uint32_t j = insert_zeros((uint32_t)i, mask) | cin;
     const C p0 = ps[j], p1 = ps[j | B], l0 = la[j], l1 = la[j | B];
     // q = P psi on the pair
@@ -235,7 +242,7 @@ __global__ __launch_bounds__(256) void k_tile(typename CT<R>::C* __restrict__ ps
 
   const int tid = threadIdx.x;
   const int L = g.L, H = g.H, m = g.m;
-  for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
+  for (int hc = tid; hc < (1 << H); hc += kThreads) {
     uint64_t off = 0;
     for (int i = 0; i < H; ++i)
       if ((hc >> i) & 1) off |= 1ull << g.hbits[i];
@@ -246,7 +253,7 @@ __global__ __launch_bounds__(256) void k_tile(typename CT<R>::C* __restrict__ ps
 
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t base = tile_base((uint64_t)t, g);
-    for (int e = tid * VW; e < M; e += blockDim.x * VW) {
+    for (int e = tid * VW; e < M; e += kThreads * VW) {
       const uint64_t a = base | hoff[e >> L] | (uint64_t)(e & lomask);
       *reinterpret_cast<VT*>(t1 + e) = *reinterpret_cast<const VT*>(psi + a);
       if (TWO) *reinterpret_cast<VT*>(t2 + e) = *reinterpret_cast<const VT*>(lam + a);
@@ -308,7 +315,7 @@ __global__ __launch_bounds__(256) void k_tile(typename CT<R>::C* __restrict__ ps
             Ash = s * scl;
           }
           __syncthreads();
-          for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
+          for (int hc = tid; hc < (1 << H); hc += kThreads) {
             double a = Ash;
             for (int i = 0; i < H; ++i)
               if ((hc >> i) & 1) a += nu[L + i];
@@ -329,7 +336,7 @@ __global__ __launch_bounds__(256) void k_tile(typename CT<R>::C* __restrict__ ps
           }
           const C* qt = reinterpret_cast<const C*>(dp.qtab) + rec.qtab_off;
           const double* qa = dp.qang + rec.qtab_off;
-          for (int e = tid * VW; e < M; e += blockDim.x * VW) {
+          for (int e = tid * VW; e < M; e += kThreads * VW) {
 #pragma unroll
             for (int v = 0; v < VW; ++v) {
               const int j = e + v;
@@ -355,7 +362,7 @@ __global__ __launch_bounds__(256) void k_tile(typename CT<R>::C* __restrict__ ps
       __syncthreads();
     }
 
-    for (int e = tid * VW; e < M; e += blockDim.x * VW) {
+    for (int e = tid * VW; e < M; e += kThreads * VW) {
       const uint64_t a = base | hoff[e >> L] | (uint64_t)(e & lomask);
       *reinterpret_cast<VT*>(psi + a) = *reinterpret_cast<const VT*>(t1 + e);
       if (TWO) *reinterpret_cast<VT*>(lam + a) = *reinterpret_cast<const VT*>(t2 + e);
@@ -410,21 +417,21 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::C* __restrict__ ps
   __shared__ int tau[kMaxQubits];
   __shared__ int hb[kMaxTileBits];
   const int tid = threadIdx.x, L = g.L, H = g.H;
-  for (int b = tid; b < g.n; b += blockDim.x) {
+  for (int b = tid; b < g.n; b += kThreads) {
     loc[b] = b < L ? b : -1;
     tau[b] = pa.tau[b];
   }
   if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
   __syncthreads();
   if (tid < H) loc[hb[tid]] = L + tid;
-  for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
+  for (int hc = tid; hc < (1 << H); hc += kThreads) {
     uint64_t off = 0;
     for (int i = 0; i < H; ++i)
       if ((hc >> i) & 1) off |= 1ull << g.hbits[i];
     hoff[hc] = off;
   }
   __syncthreads();
-  for (int j = tid; j < M; j += blockDim.x) {
+  for (int j = tid; j < M; j += kThreads) {
     uint32_t lj = 0;
     for (int i = 0; i < g.m; ++i)
       if ((j >> i) & 1) {
@@ -455,7 +462,7 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::C* __restrict__ ps
     VT ba[kMaxLd], bb[kMaxLd];  // every load of both tiles is issued before the LDS writes
 #pragma unroll
     for (int u = 0; u < kMaxLd; ++u) {
-      const int e = (u * (int)blockDim.x + tid) * VW;
+      const int e = (u * kThreads + tid) * VW;
       if (NLD > 0 || e < M) {  // a self-paired tile is simply read twice
         ba[u] = *reinterpret_cast<const VT*>(psi + (base | off(e)));
         bb[u] = *reinterpret_cast<const VT*>(psi + (pbase | off(e)));
@@ -463,7 +470,7 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::C* __restrict__ ps
     }
 #pragma unroll
     for (int u = 0; u < kMaxLd; ++u) {
-      const int e = (u * (int)blockDim.x + tid) * VW;
+      const int e = (u * kThreads + tid) * VW;
       if (NLD > 0 || e < M) {
         *reinterpret_cast<VT*>(ta + swz<R>(e)) = ba[u];
         *reinterpret_cast<VT*>(tb + swz<R>(e)) = bb[u];
@@ -472,7 +479,7 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::C* __restrict__ ps
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kMaxLd; ++u) {
-      const int e = (u * (int)blockDim.x + tid) * VW;
+      const int e = (u * kThreads + tid) * VW;
       if (NLD > 0 || e < M) {
         *reinterpret_cast<VT*>(psi + (pbase | off(e))) = gather_vec<R>(ta, ltau, e);
         if (!self) *reinterpret_cast<VT*>(psi + (base | off(e))) = gather_vec<R>(tb, ltau, e);
@@ -488,11 +495,11 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::C* __restrict__ ps
 template <typename R>
 __global__ void k_fill(typename CT<R>::C* psi, int64_t N, double re) {
   using C = typename CT<R>::C;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < N; i += (int64_t)gridDim.x * kThreads)
     psi[i] = mk<C>(re, 0.0);
 }
 __global__ void k_zero(double* p, int64_t count) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < count; i += (int64_t)gridDim.x * kThreads)
     p[i] = 0.0;
 }
 
@@ -518,7 +525,7 @@ __global__ __launch_bounds__(256) void k_sumsq(const typename CT<R>::C* __restri
   const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
   const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < N ? lo + chunk : N;
   double acc = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
     const auto v = psi[i];
     acc += (double)v.x * v.x + (double)v.y * v.y;
   }
@@ -534,7 +541,7 @@ __global__ __launch_bounds__(256) void k_dot_re(const typename CT<R>::C* __restr
   const int64_t chunk = (N + gridDim.x - 1) / gridDim.x;
   const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < N ? lo + chunk : N;
   double acc = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
     const auto u = a[i], v = b[i];
     acc += (double)u.x * v.x + (double)u.y * v.y;
   }
@@ -574,7 +581,7 @@ __global__ __launch_bounds__(256) void k_expect_poly(const typename CT<R>::C* __
   const int lb = n < LB ? n : LB;
   const int rows = 1 << lb;
   const int64_t ntiles = 1ll << (n - lb);
-  for (int j = tid; j < rows; j += blockDim.x) sElo[j] = elo[j];
+  for (int j = tid; j < rows; j += kThreads) sElo[j] = elo[j];
   const double* mu = poly + 1;
   const double* lam = poly + 1 + n;
   double acc = 0.0;
@@ -611,7 +618,7 @@ __global__ __launch_bounds__(256) void k_expect_poly(const typename CT<R>::C* __
     }
     __syncthreads();
     const double A = sA;
-    for (int j = tid; j < rows; j += blockDim.x) {
+    for (int j = tid; j < rows; j += kThreads) {
       const auto v = psi[hbits | (uint64_t)j];
       const double e = A + sElo[j] + N1[j & 63] + N2[j >> 6];
       acc += ((double)v.x * v.x + (double)v.y * v.y) * e;
@@ -646,7 +653,7 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
   const int64_t ntiles = 1ll << (ps.n - m);
   const uint32_t lomask = (1u << L) - 1u;
   if (tid < kPauliMaxH) hb[tid] = ps.hbits[tid];
-  for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
+  for (int hc = tid; hc < (1 << H); hc += kThreads) {
     uint64_t off = 0;
     for (int i = 0; i < H; ++i)
       if ((hc >> i) & 1) off |= 1ull << ps.hbits[i];
@@ -657,7 +664,7 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     uint64_t base = (uint64_t)t << L;
     for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
-    for (int j = tid; j < M; j += blockDim.x) tile[j] = psi[base | hoff[j >> L] | (uint64_t)(j & lomask)];
+    for (int j = tid; j < M; j += kThreads) tile[j] = psi[base | hoff[j >> L] | (uint64_t)(j & lomask)];
     __syncthreads();
     R ar[EPT], ai[EPT];
 #pragma unroll
@@ -673,7 +680,7 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
         const uint32_t zl = T.zl;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-          const int y = tid + e * (int)blockDim.x;
+          const int y = tid + e * kThreads;
           if (y < M) {
             const uint32_t x = (uint32_t)y ^ G.fl;
             const C px = tile[x];
@@ -687,7 +694,7 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
     }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const int y = tid + e * (int)blockDim.x;
+      const int y = tid + e * kThreads;
       if (y < M) {
         const C py = tile[y];
         acc += (double)py.x * ar[e] + (double)py.y * ai[e];
@@ -719,7 +726,7 @@ __global__ __launch_bounds__(256) void k_pauli_far(const typename CT<R>::C* __re
   __shared__ double red[8];
   const int64_t N = 1ll << n;
   double acc = 0.0;
-  for (int64_t y = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; y < N; y += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t y = blockIdx.x * (int64_t)kThreads + threadIdx.x; y < N; y += (int64_t)gridDim.x * kThreads) {
     const uint64_t x = (uint64_t)y ^ flip;
     double fr, fi;
     pauli_factor(x, terms, nt, fr, fi);
@@ -742,7 +749,7 @@ __global__ __launch_bounds__(256) void k_pauli_far(const typename CT<R>::C* __re
 __global__ __launch_bounds__(256) void k_final_sum(const double* __restrict__ part, int count, double* out) {
   __shared__ double red[8];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += part[i];
+  for (int i = threadIdx.x; i < count; i += kThreads) acc += part[i];
   const double r = block_sum(acc, red);
   if (threadIdx.x == 0) out[0] = r;
 }
@@ -752,7 +759,7 @@ __global__ __launch_bounds__(256) void k_slot_sums(const double* __restrict__ pa
   __shared__ double red[8];
   double acc = 0.0;
   const double* p = part + (int64_t)blockIdx.x * stride;
-  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) acc += p[i];
+  for (int i = threadIdx.x; i < nblocks; i += kThreads) acc += p[i];
   const double r = block_sum(acc, red);
   if (threadIdx.x == 0) out[blockIdx.x] = r;
 }
@@ -790,7 +797,7 @@ __device__ __forceinline__ double lane_mass(const typename CT<R>::C* psi, int64_
 template <typename R>
 __global__ __launch_bounds__(256) void k_samp_blocks(const typename CT<R>::C* __restrict__ psi, int64_t N,
                                                      int64_t nb, double* __restrict__ S) {
-  const int64_t blk = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t blk = blockIdx.x * (int64_t)(kThreads >> 6) + (threadIdx.x >> 6);
   if (blk >= nb) return;
   const int lane = threadIdx.x & 63;
   const double incl = wave_incl_scan(lane_mass<R>(psi, N, blk, lane));
@@ -857,7 +864,7 @@ __global__ __launch_bounds__(256) void k_samp_shots(const typename CT<R>::C* __r
                                                     uint64_t seed, const double* __restrict__ uni,
                                                     const SampArgs sa, int64_t* __restrict__ out) {
   using C = typename CT<R>::C;
-  const int64_t j = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t j = blockIdx.x * (int64_t)(kThreads >> 6) + (threadIdx.x >> 6);
   if (j >= shots) return;
   const int lane = threadIdx.x & 63;
   const double u = uni ? uni[j] : philox_uniform((uint64_t)j, seed);
@@ -1242,6 +1249,7 @@ struct PassSmem {
   double phA0[kMaxPhasePerPass];
   double phNu0[kMaxPhasePerPass][kMaxTileBits];
   double phCk[kMaxPhasePerPass][kMaxKBits];
+  uint32_t phS[kMaxPhasePerPass];  // bit b: phNu[p][b] / pi odd; bit 31: phA[p] / pi odd
   int hb[kMaxTileBits];
   int kpos[kMaxKBits];
 };
@@ -1284,8 +1292,9 @@ __device__ __forceinline__ void pass_body(
   const int nph = g.nph, ph0 = g.ph0, nst = g.nst, st0 = g.st0, op0 = g.op0;
   const int kb = (n - m) - gbits;
   if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
+  if (tid < kMaxPhasePerPass) sm.phS[tid] = 0u;
   if (TWO)
-    for (int i = tid; i < kMaxGradPerPass * (kThreads / 64); i += blockDim.x) gacc[i] = 0.0;
+    for (int i = tid; i < kMaxGradPerPass * (kThreads / 64); i += kThreads) gacc[i] = 0.0;
   if (tid == 0) {  // global positions of the tile-index bits above the grid
     int idx = 0;
     uint64_t tm = (1ull << L) - 1;
@@ -1296,7 +1305,7 @@ __device__ __forceinline__ void pass_body(
       ++idx;
     }
   }
-  for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
+  for (int hc = tid; hc < (1 << H); hc += kThreads) {
     uint64_t off = 0;
     for (int i = 0; i < H; ++i)
       if ((hc >> i) & 1) off |= 1ull << g.hbits[i];
@@ -1312,14 +1321,14 @@ __device__ __forceinline__ void pass_body(
     return b;
   };
   auto gaddr = [&](uint64_t b, int u) {
-    const int e = (u * (int)blockDim.x + tid) * VW;
+    const int e = (u * kThreads + tid) * VW;
     return b | hoff[e >> L] | (uint64_t)(e & lomask);
   };
   // phase polynomials, part fixed for this workgroup (tile t0 = blockIdx.x,
   // k bits zero): constant, tile-bit coefficients and k-bit coefficients
   {
     const uint64_t base0 = tbase(t_first);
-    for (int idx = tid; idx < nph * 32; idx += blockDim.x) {
+    for (int idx = tid; idx < nph * 32; idx += kThreads) {
       const int p = idx >> 5, r = idx & 31;
       const PhaseRec rec = phases[phlist[ph0 + p]];
       const double* P = dpool + rec.dpool;
@@ -1348,25 +1357,49 @@ __device__ __forceinline__ void pass_body(
     __syncthreads();
   }
 
+  // the two-state pass runs two workgroups per CU (its tiles fill the LDS),
+  // too few to hide the loads behind another workgroup's arithmetic: it
+  // loads the next tile into registers while the current one is processed
+  // (not in the variant with controls, whose registers are already full)
+  constexpr bool PF = TWO && !GUARD && !CTRL;
+  using NV = typename CT<R>::NV;  // native vector: stays in registers when indexed
+  NV pre[PF ? 2 * NLD : 1];
+#define QS_PREFETCH(TT)                                                                     \
+  {                                                                                         \
+    const uint64_t pb = tbase(TT);                                                          \
+    _Pragma("unroll") for (int u = 0; u < NLD; ++u) pre[u] = *reinterpret_cast<const NV*>(psi + gaddr(pb, u)); \
+    _Pragma("unroll") for (int u = 0; u < NLD; ++u) pre[NLD + u] = *reinterpret_cast<const NV*>(lam + gaddr(pb, u)); \
+  }
+  if (PF && t_first < ntiles) QS_PREFETCH(t_first);
+
   for (int64_t t = t_first; t < ntiles; t += t_step) {
     const uint64_t base = tbase(t);
-    for (int half = 0; half < (TWO ? 2 : 1); ++half) {
-      const C* src = half ? lam : psi;
-      C* dst = half ? t2 : t1;
-      VT buf[NLD];  // issue every load of the tile before the first LDS write
+    if (PF) {
 #pragma unroll
-      for (int u = 0; u < NLD; ++u)
-        if (!GUARD || (u * (int)blockDim.x + tid) * VW < M) buf[u] = *reinterpret_cast<const VT*>(src + gaddr(base, u));
+      for (int u = 0; u < NLD; ++u) {
+        const int e = swz<R>((u * kThreads + tid) * VW);
+        *reinterpret_cast<NV*>(t1 + e) = pre[u];
+        *reinterpret_cast<NV*>(t2 + e) = pre[NLD + u];
+      }
+    } else {
+      for (int half = 0; half < (TWO ? 2 : 1); ++half) {
+        const C* src = half ? lam : psi;
+        C* dst = half ? t2 : t1;
+        VT buf[NLD];  // issue every load of the tile before the first LDS write
 #pragma unroll
-      for (int u = 0; u < NLD; ++u)
-        if (!GUARD || (u * (int)blockDim.x + tid) * VW < M)
-          *reinterpret_cast<VT*>(dst + swz<R>((u * (int)blockDim.x + tid) * VW)) = buf[u];
+        for (int u = 0; u < NLD; ++u)
+          if (!GUARD || (u * kThreads + tid) * VW < M) buf[u] = *reinterpret_cast<const VT*>(src + gaddr(base, u));
+#pragma unroll
+        for (int u = 0; u < NLD; ++u)
+          if (!GUARD || (u * kThreads + tid) * VW < M)
+            *reinterpret_cast<VT*>(dst + swz<R>((u * kThreads + tid) * VW)) = buf[u];
+      }
     }
     // per-tile coefficients of the pass's phase polynomials (the part of theta
     // fixed by the bits outside the tile) from the workgroup part and the k bits
     {
       const uint32_t kk = (uint32_t)((uint64_t)t >> gbits);
-      for (int idx = tid; idx < nph * 16; idx += blockDim.x) {
+      for (int idx = tid; idx < nph * 16; idx += kThreads) {
         const int p = idx >> 4, b = idx & 15;
         const PhaseRec rec = phases[phlist[ph0 + p]];
         const double scl = (rec.scale_idx >= 0 ? scales[rec.scale_idx] : 1.0) * (TWO ? -1.0 : 1.0);
@@ -1379,6 +1412,7 @@ __device__ __forceinline__ void pass_body(
           const double a = phNu0[p][b] + scl * s;
           phNu[p][b] = a;
           en[p * kEnRow + b] = expi<C>(a);
+          if (pi_parity(a)) atomicOr(&sm.phS[p], 1u << b);
         } else if (b == 15) {
           double s = phA0[p];
 #pragma unroll
@@ -1387,10 +1421,13 @@ __device__ __forceinline__ void pass_body(
           const double a = s + scl * kt[m * kMaxKBits + kk];
           phA[p] = a;
           en[p * kEnRow + kMaxTileBits] = expi<C>(a);
+          if (pi_parity(a)) atomicOr(&sm.phS[p], 1u << 31);
         }
       }
       __syncthreads();
     }
+    if (PF && t + t_step < ntiles) QS_PREFETCH(t + t_step);  // the LDS copies of pre are done
+#undef QS_PREFETCH
 
     for (int si = 0; si < nst; ++si) {
       const StageRec st = stages[st0 + (TWO ? nst - 1 - si : si)];
@@ -1412,7 +1449,7 @@ __device__ __forceinline__ void pass_body(
       };
       char* const b1 = reinterpret_cast<char*>(t1);
       char* const b2 = reinterpret_cast<char*>(t2);
-      for (int gb = 0; gb < (M >> NR); gb += blockDim.x) {
+      for (int gb = 0; gb < (M >> NR); gb += kThreads) {
         const bool valid = !GUARD || gb + tid < (M >> NR);
         const uint32_t jg = valid ? insert_zeros((uint32_t)(gb + tid), st.rbmask) : 0u;
         const int grp = valid ? gb + tid : 0;  // per-group table row (threads past the tile read row 0)
@@ -1432,24 +1469,30 @@ __device__ __forceinline__ void pass_body(
         // addresses instead of keeping sixteen of them live across the ops
         asm volatile("" : "+v"(A));
         // sign mask of a phase whose coefficients are all multiples of pi:
-        // the factor of register element e is (-1)^bit e
+        // the factor of register element e is (-1)^bit e.  Every angle is a
+        // multiple of pi, so the parity of a sum is the XOR of the parities:
+        // tile part from phS, group part from the bit-sliced table (one
+        // 64-bit word per wave and slice: scalar loads)
         auto sign_mask = [&](const TileOp& op, const StageRec& sr, int grp, uint32_t jgl) -> uint32_t {
           const int p = op.pidx;
           const PhaseRec rec = phases[op.aux];
-          const double* bt = btab + rec.bt_off + grp * (NR + 1);
+          const int nw = ((M >> NR) + 63) >> 6;
+          const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)grp >> 6);
+          const uint64_t* sb = reinterpret_cast<const uint64_t*>(btab + rec.bt_off) + wv;
+          const uint32_t ln = (uint32_t)grp & 63u;
+          auto gbit = [&](int sl) { return (uint32_t)(sb[sl * nw] >> ln) & 1u; };
+          const uint32_t ts = sm.phS[p];
           uint32_t S;
           if (op.flags & 2u) {
             const int kbs = op.b[0];
             const int rbk = kbs == 0 ? sr.rb[0] : kbs == 1 ? sr.rb[1] : kbs == 2 ? sr.rb[2] : sr.rb[3];
-            S = pi_parity(phNu[p][rbk] + bt[1 + kbs]) ? slot_pattern(kbs) : 0u;
+            S = (((ts >> rbk) ^ gbit(1 + kbs)) & 1u) ? slot_pattern(kbs) : 0u;
           } else {
-            double th = phA[p] + bt[0];
-            for (uint32_t r = jgl; r; r &= r - 1) th += phNu[p][__builtin_ctz(r)];
-            S = pi_parity(th) ? 0xFFFFu : 0u;
-            if (pi_parity(phNu[p][sr.rb[0]] + bt[1])) S ^= 0xAAAAu;
-            if (pi_parity(phNu[p][sr.rb[1]] + bt[2])) S ^= 0xCCCCu;
-            if (pi_parity(phNu[p][sr.rb[2]] + bt[3])) S ^= 0xF0F0u;
-            if (pi_parity(phNu[p][sr.rb[3]] + bt[4])) S ^= 0xFF00u;
+            S = (((uint32_t)__builtin_popcount(ts & jgl) ^ (ts >> 31) ^ gbit(0)) & 1u) ? 0xFFFFu : 0u;
+            if (((ts >> sr.rb[0]) ^ gbit(1)) & 1u) S ^= 0xAAAAu;
+            if (((ts >> sr.rb[1]) ^ gbit(2)) & 1u) S ^= 0xCCCCu;
+            if (((ts >> sr.rb[2]) ^ gbit(3)) & 1u) S ^= 0xF0F0u;
+            if (((ts >> sr.rb[3]) ^ gbit(4)) & 1u) S ^= 0xFF00u;
           }
           return S ^ (uint32_t)rec.wr_sign;
         };
@@ -1616,6 +1659,7 @@ __device__ __forceinline__ void pass_body(
       }
       __syncthreads();
     }
+    if (tid < nph) sm.phS[tid] = 0u;  // the stages are done with it; the next tile ORs afresh
 
     for (int half = 0; half < (TWO ? 2 : 1); ++half) {
       C* dstg = half ? lam : psi;
@@ -1623,16 +1667,16 @@ __device__ __forceinline__ void pass_body(
       VT buf[NLD];
 #pragma unroll
       for (int u = 0; u < NLD; ++u)
-        if (!GUARD || (u * (int)blockDim.x + tid) * VW < M)
-          buf[u] = *reinterpret_cast<const VT*>(src + swz<R>((u * (int)blockDim.x + tid) * VW));
+        if (!GUARD || (u * kThreads + tid) * VW < M)
+          buf[u] = *reinterpret_cast<const VT*>(src + swz<R>((u * kThreads + tid) * VW));
 #pragma unroll
       for (int u = 0; u < NLD; ++u)
-        if (!GUARD || (u * (int)blockDim.x + tid) * VW < M) *reinterpret_cast<VT*>(dstg + gaddr(base, u)) = buf[u];
+        if (!GUARD || (u * kThreads + tid) * VW < M) *reinterpret_cast<VT*>(dstg + gaddr(base, u)) = buf[u];
     }
     __syncthreads();
   }
   if (TWO) {  // the partials are complete after the last barrier above
-    for (int i = tid; i < g.nops * (kThreads / 64); i += blockDim.x) {
+    for (int i = tid; i < g.nops * (kThreads / 64); i += kThreads) {
       const int oi = i / (kThreads / 64), w = i % (kThreads / 64);
       const TileOp& op = ops[op0 + oi];
       if (op.kind == OP_ROT && op.gslot >= 0)
@@ -1715,7 +1759,7 @@ __global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ ps
   const int L = g.L, H = g.H, m = g.m;
   if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
   __syncthreads();
-  for (int hc = tid; hc < (1 << H); hc += blockDim.x) {
+  for (int hc = tid; hc < (1 << H); hc += kThreads) {
     uint64_t off = 0;
     for (int i = 0; i < H; ++i)
       if ((hc >> i) & 1) off |= 1ull << hb[i];
@@ -1724,14 +1768,14 @@ __global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ ps
   uint32_t tmask = 0;
 #pragma unroll
   for (int t = 0; t < K; ++t) tmask |= 1u << ma.tl[t];
-  for (int r = tid; r < D; r += blockDim.x) {
+  for (int r = tid; r < D; r += kThreads) {
     uint32_t o = 0;
 #pragma unroll
     for (int t = 0; t < K; ++t)
       if ((r >> (K - 1 - t)) & 1) o |= 1u << ma.tl[t];
     rowoff[r] = o;
   }
-  for (int c = tid; c < NCOL; c += blockDim.x) coloff[c] = insert_zeros((uint32_t)c, tmask);
+  for (int c = tid; c < NCOL; c += kThreads) coloff[c] = insert_zeros((uint32_t)c, tmask);
   // A fragments of the realified gate, resident for the whole launch
   R a[RB][KS];
 #pragma unroll
@@ -1752,16 +1796,16 @@ __global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ ps
     VT buf[NLD];
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-      const int e = (u * (int)blockDim.x + tid) * VW;
+      const int e = (u * kThreads + tid) * VW;
       buf[u] = *reinterpret_cast<const VT*>(psi + (base | hoff[e >> L] | (uint64_t)(e & lomask)));
     }
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-      const int e = (u * (int)blockDim.x + tid) * VW;
+      const int e = (u * kThreads + tid) * VW;
       *reinterpret_cast<VT*>(tile + swz<R>(e)) = buf[u];
     }
     __syncthreads();
-    for (int cb = wave; cb < NCOL / 16; cb += (int)(blockDim.x >> 6)) {
+    for (int cb = wave; cb < NCOL / 16; cb += (int)(kThreads >> 6)) {
       const uint32_t co = coloff[16 * cb + (lane & 15)];
       Acc acc[RB];
 #pragma unroll
@@ -1787,12 +1831,12 @@ __global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ ps
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-      const int e = (u * (int)blockDim.x + tid) * VW;
+      const int e = (u * kThreads + tid) * VW;
       buf[u] = *reinterpret_cast<const VT*>(tile + swz<R>(e));
     }
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-      const int e = (u * (int)blockDim.x + tid) * VW;
+      const int e = (u * kThreads + tid) * VW;
       *reinterpret_cast<VT*>(psi + (base | hoff[e >> L] | (uint64_t)(e & lomask))) = buf[u];
     }
     __syncthreads();
@@ -1841,19 +1885,19 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
     C* lam = reinterpret_cast<C*>(a.states) + in.lam_off;
     const int64_t N = 1ll << in.n;
     const double* par = a.params + in.param_base;
-    for (int o = tid; o < in.nops; o += blockDim.x) {
+    for (int o = tid; o < in.nops; o += kThreads) {
       const TileOp op = a.dp.ops[in.ops_base + o];
       if (op.kind == OP_ROT && op.mat >= 0) rot_fill(matc + in.mat_base + op.mat, op.pauli, par[op.pidx]);
     }
-    for (int64_t x = tid; x < N; x += blockDim.x) psi[x] = mk<C>(x == 0 ? 1.0 : 0.0, 0.0);
+    for (int64_t x = tid; x < N; x += kThreads) psi[x] = mk<C>(x == 0 ? 1.0 : 0.0, 0.0);
     double* gp = a.gpart + (int64_t)in.slot_base * 4;
-    for (int j = tid; j < in.nslots * 4; j += blockDim.x) gp[j] = 0.0;
+    for (int j = tid; j < in.nslots * 4; j += kThreads) gp[j] = 0.0;
     __syncthreads();
     for (int dir = 0; dir < 2; ++dir) {
       if (dir == 1) {
         // energy of the diagonal observable and lambda = H psi
         double acc = 0.0;
-        for (int64_t x = tid; x < N; x += blockDim.x) {
+        for (int64_t x = tid; x < N; x += kThreads) {
           double d = 0.0;
           for (int t = 0; t < in.obs_nterms; ++t) {
             const PauliTermDev T = a.terms[in.obs_off + t];
@@ -1908,7 +1952,7 @@ __global__ void k_phase_tabs(const PhaseRec* __restrict__ phases, const double* 
   if (rec.scale_idx < 0 || rec.ctab_off < 0) return;
   const double sc = scales[rec.scale_idx];
   const int nb = rec.ctab_n - NE;
-  for (int i = threadIdx.x; i < rec.ctab_n; i += blockDim.x) {
+  for (int i = threadIdx.x; i < rec.ctab_n; i += kThreads) {
     const double a = i < nb ? btab[rec.bt_off + i] : qang[rec.wr_off + (i - nb)];
     ctab[rec.ctab_off + i] = expi<C>(sc * a);
   }
@@ -1919,7 +1963,7 @@ template <typename R>
 __global__ void k_rot_mats(const TileOp* __restrict__ ops, int nops, const double* __restrict__ params,
                            typename CT<R>::C* __restrict__ matc) {
   using C = typename CT<R>::C;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= nops) return;
   const TileOp op = ops[i];
   if (op.kind != OP_ROT || op.mat < 0) return;

@@ -575,28 +575,49 @@ void stage_pass(Plan& plan, Pass& ps) {
             plan.btab.push_back(q);
           }
         }
-        rec.bt_off = (int)plan.btab.size();
         const int ngr = 1 << (g.m - kRegBits);
+        std::vector<double> ang;  // per group: theta_T(jg), beta_0..beta_3
+        ang.reserve(size_t(ngr) * (kRegBits + 1));
         for (int grp = 0; grp < ngr; ++grp) {
           uint32_t jg = (uint32_t)grp;
           for (int k2 = 0; k2 < g.m; ++k2)  // insert zeros at the register bits, ascending
             if ((sr.rbmask >> k2) & 1) jg = ((jg >> k2) << (k2 + 1)) | (jg & ((1u << k2) - 1u));
-          plan.btab.push_back(plan.qang[rec.qtab_off + jg]);
+          ang.push_back(plan.qang[rec.qtab_off + jg]);
           for (int k = 0; k < kRegBits; ++k) {
             const int pk = pos(s.rb[k]);
             double b = mu[pk];
             for (uint32_t r = jg; r; r &= r - 1) b += lam[size_t(pos(__builtin_ctz(r))) * n + pk];
-            plan.btab.push_back(b);
+            ang.push_back(b);
           }
         }
-        // the same angles as unit complex factors (left zero for a scaled
-        // record: its scale is known per launch)
+        rec.bt_off = (int)plan.btab.size();
         rec.ctab_off = (int)plan.ctab.size();
-        rec.ctab_n = ngr * (kRegBits + 1) + (1 << kRegBits);
-        for (int i = 0; i < ngr * (kRegBits + 1); ++i)
-          plan.ctab.push_back(rec.scale_idx < 0 ? std::polar(1.0, plan.btab[rec.bt_off + i]) : cd(0, 0));
-        for (int e = 0; e < (1 << kRegBits); ++e)
-          plan.ctab.push_back(rec.scale_idx < 0 ? plan.qtab[rec.wr_off + e] : cd(0, 0));
+        if (op.flags & 4u) {
+          // sign op: only the parity of each angle / pi matters.  Bit-sliced,
+          // slice s (theta_T, beta_0..beta_3) holds one bit per group, 64
+          // groups a word, so a wave fetches its bits with scalar loads
+          const int nw = (ngr + 63) / 64;
+          std::vector<uint64_t> words(size_t(kRegBits + 1) * nw, 0);
+          for (int grp = 0; grp < ngr; ++grp)
+            for (int sl = 0; sl <= kRegBits; ++sl)
+              if (std::llround(ang[size_t(grp) * (kRegBits + 1) + sl] / kPi) & 1)
+                words[size_t(sl) * nw + grp / 64] |= 1ull << (grp % 64);
+          for (uint64_t w : words) {
+            double d;
+            std::memcpy(&d, &w, sizeof d);  // raw bits in the double pool
+            plan.btab.push_back(d);
+          }
+          rec.ctab_n = 0;
+        } else {
+          plan.btab.insert(plan.btab.end(), ang.begin(), ang.end());
+          // the same angles as unit complex factors (left zero for a scaled
+          // record: its scale is known per launch)
+          rec.ctab_n = ngr * (kRegBits + 1) + (1 << kRegBits);
+          for (int i = 0; i < ngr * (kRegBits + 1); ++i)
+            plan.ctab.push_back(rec.scale_idx < 0 ? std::polar(1.0, ang[i]) : cd(0, 0));
+          for (int e = 0; e < (1 << kRegBits); ++e)
+            plan.ctab.push_back(rec.scale_idx < 0 ? plan.qtab[rec.wr_off + e] : cd(0, 0));
+        }
       }
       if (op.kind != OP_PHASE) op.flags = 0;
       if (op.kind == OP_ROT && op.pauli == 2) op.flags |= 1u;

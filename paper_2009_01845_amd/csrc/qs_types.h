@@ -74,13 +74,15 @@ struct PhaseRec {
   int32_t qtab_off;  // offset in the complex phase-table pool
   int32_t scale_idx; // -1: scale 1; else theta is multiplied by scales[scale_idx]
   int32_t wr_off;    // staged passes: exp(i Q_R(e)) over the register slots, 2^kRegBits entries
-  int32_t bt_off;    // staged passes: per thread group (theta_T(jg), beta_0..beta_3) pass constants
+  int32_t bt_off;    // staged passes: per thread group (theta_T(jg), beta_0..beta_3) pass constants;
+                     // sign ops keep only their parities / pi, bit-sliced: word [s][grp / 64],
+                     // bit grp % 64, stored as raw 64-bit patterns
   int32_t wr_trivial;  // 1 when Q_R(e) is zero for every e
   int32_t kt_off;    // staged passes: lam(tile bit b, k-bit j) [m][kMaxKBits], then Q_k(kk) [2^kb]
   int32_t wr_sign;   // sign ops: bit e = parity of Q_R(e) / pi
   int32_t ctab_off;  // staged passes: complex factors in the state precision, per thread group
                      // exp(i beta_0..4) [ngroups][kRegBits + 1], then exp(i Q_R(e)) [2^kRegBits]
-  int32_t ctab_n;    // entries at ctab_off (scaled records are filled per launch)
+  int32_t ctab_n;    // entries at ctab_off (scaled records are filled per launch; 0 for sign ops)
 };
 
 // Per-pass geometry.
