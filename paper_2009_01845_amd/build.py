@@ -32,6 +32,10 @@ FLAGS = [
     # into one block turns register-array accesses into pointer selects,
     # which forces the arrays into scratch memory
     "-mllvm", "-simplifycfg-sink-common=false",
+    # branch on uniform values with scalar branches and leave those regions
+    # unstructurized: structurizing the op dispatch of the staged pass routes
+    # the register array through flow blocks and costs a full copy per op
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -58,6 +58,51 @@ template <typename C> __device__ __forceinline__ C cconj(C a) {
   return a;
 }
 
+// In-place register updates.  An op loop that dispatches over many kinds of
+// gate keeps its register array in one set of registers only if every case
+// leaves each new value in the register of the old value it replaces;
+// otherwise the compiler gives the cases a second array and moves it back
+// after every op.  The compiler's own choice, an FMA that accumulates into
+// the temporary holding the cross terms, puts the result in the wrong
+// register, so the finishing FMA is written with its destination tied to
+// the replaced value (VOP3 form).  The cross terms are computed first: they
+// pass through an empty asm that the finishing FMAs depend on.
+template <typename T> __device__ __forceinline__ void after2(T& a, T& b) { asm("" : "+v"(a), "+v"(b)); }
+template <typename T> __device__ __forceinline__ void after4(T& a, T& b, T& c, T& d) {
+  asm("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+}
+// d = x * m + t, in the register of d (whose old value is dead)
+__device__ __forceinline__ void fma_to(float& d, float x, float m, float t) {
+  asm("v_fma_f32 %0, %1, %2, %3" : "+v"(d) : "v"(x), "v"(m), "v"(t));
+}
+__device__ __forceinline__ void fma_to(double& d, double x, double m, double t) {
+  asm("v_fma_f64 %0, %1, %2, %3" : "+v"(d) : "v"(x), "v"(m), "v"(t));
+}
+// a = a * m + t, in the register of a
+__device__ __forceinline__ void fma_self(float& a, float m, float t) {
+  asm("v_fma_f32 %0, %0, %1, %2" : "+v"(a) : "v"(m), "v"(t));
+}
+__device__ __forceinline__ void fma_self(double& a, double m, double t) {
+  asm("v_fma_f64 %0, %0, %1, %2" : "+v"(a) : "v"(m), "v"(t));
+}
+// v *= f
+template <typename C> __device__ __forceinline__ void cmul_ip(C& v, C f) {
+  auto vx = v.x, vy = v.y;
+  auto t1 = -vy * f.y, t2 = vy * f.x;
+  after2(t1, t2);
+  fma_to(vy, vx, f.y, t2);  // the new y is formed before x is overwritten
+  fma_self(vx, f.x, t1);
+  v.x = vx;
+  v.y = vy;
+}
+// (a, b) <- (m00 a + m01 b, m10 a + m11 b), real coefficients
+template <typename T> __device__ __forceinline__ void mix2(T& a, T& b, T m00, T m01, T m10, T m11) {
+  auto ta = m01 * b, tb = m10 * a;
+  after2(ta, tb);
+  fma_self(a, m00, ta);
+  fma_self(b, m11, tb);
+}
+
 __device__ __forceinline__ uint32_t insert_zeros(uint32_t i, uint32_t mask) {
   while (mask) {
     const int p = __builtin_ctz(mask);
@@ -949,16 +994,27 @@ __device__ __forceinline__ void r1(C* v, C m00, C m01, C m10, C m11, uint32_t cr
     if (e & (1 << K)) continue;
     if (CTRL && (e & creg) != creg) continue;
     const int f = e | (1 << K);
-    const C a = v[e], b = v[f];
+    auto ax = v[e].x, ay = v[e].y, bx = v[f].x, by = v[f].y;
     if (REAL) {
-      v[e].x = m00.x * a.x + m01.x * b.x;
-      v[e].y = m00.x * a.y + m01.x * b.y;
-      v[f].x = m10.x * a.x + m11.x * b.x;
-      v[f].y = m10.x * a.y + m11.x * b.y;
+      mix2(ax, bx, m00.x, m01.x, m10.x, m11.x);
+      mix2(ay, by, m00.x, m01.x, m10.x, m11.x);
     } else {
-      v[e] = cmadd(cmul(m00, a), m01, b);
-      v[f] = cmadd(cmul(m10, a), m11, b);
+      // every output reads all four inputs: the three terms without the
+      // replaced input first, then the finishing FMA
+      auto tax = -m00.y * ay + m01.x * bx - m01.y * by;
+      auto tay = m00.y * ax + m01.x * by + m01.y * bx;
+      auto tbx = m10.x * ax - m10.y * ay - m11.y * by;
+      auto tby = m10.x * ay + m10.y * ax + m11.y * bx;
+      after4(tax, tay, tbx, tby);
+      fma_self(ax, m00.x, tax);
+      fma_self(ay, m00.x, tay);
+      fma_self(bx, m11.x, tbx);
+      fma_self(by, m11.x, tby);
     }
+    v[e].x = ax;
+    v[e].y = ay;
+    v[f].x = bx;
+    v[f].y = by;
   }
 }
 
@@ -987,20 +1043,37 @@ __device__ __forceinline__ void r2(C* v, const C* __restrict__ mm, uint32_t creg
   for (int e = 0; e < NE; ++e) {
     if (e & ((1 << KH) | (1 << KL))) continue;
     if (CTRL && (e & creg) != creg) continue;
-    const int i1 = e | (1 << KL), i2 = e | (1 << KH), i3 = i1 | i2;
-    const C a0 = v[e], a1 = v[i1], a2 = v[i2], a3 = v[i3];
-    C o[4];
+    const int idx[4] = {e, e | (1 << KL), e | (1 << KH), e | (1 << KL) | (1 << KH)};
+    decltype(C().x) x[4], y[4], tx[4], ty[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      C acc = cmul(mm[4 * r], a0);
-      acc = cmadd(acc, mm[4 * r + 1], a1);
-      acc = cmadd(acc, mm[4 * r + 2], a2);
-      o[r] = cmadd(acc, mm[4 * r + 3], a3);
+      x[r] = v[idx[r]].x;
+      y[r] = v[idx[r]].y;
     }
-    v[e] = o[0];
-    v[i1] = o[1];
-    v[i2] = o[2];
-    v[i3] = o[3];
+    // output r without its diagonal term on the component it replaces
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const C d = mm[4 * r + r];
+      tx[r] = -d.y * y[r];
+      ty[r] = d.y * x[r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c == r) continue;
+        const C m = mm[4 * r + c];
+        tx[r] += m.x * x[c] - m.y * y[c];
+        ty[r] += m.x * y[c] + m.y * x[c];
+      }
+    }
+    after4(tx[0], tx[1], tx[2], tx[3]);
+    after4(ty[0], ty[1], ty[2], ty[3]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const auto dx = mm[4 * r + r].x;
+      fma_self(x[r], dx, tx[r]);
+      fma_self(y[r], dx, ty[r]);
+      v[idx[r]].x = x[r];
+      v[idx[r]].y = y[r];
+    }
   }
 }
 
@@ -1081,17 +1154,19 @@ __device__ __forceinline__ void r1x(C* v, C m00, C m01) {
   for (int e = 0; e < NE; ++e) {
     if (e & (1 << K)) continue;
     const int f = e | (1 << K);
-    const C p = v[e], q = v[f];
-    v[e].x = a * p.x - t * q.y;
-    v[e].y = a * p.y + t * q.x;
-    v[f].x = a * q.x - t * p.y;
-    v[f].y = a * q.y + t * p.x;
+    auto px = v[e].x, py = v[e].y, qx = v[f].x, qy = v[f].y;
+    mix2(px, qy, a, -t, t, a);  // (p.x, q.y) and (p.y, q.x) mix separately
+    mix2(py, qx, a, t, -t, a);
+    v[e].x = px;
+    v[e].y = py;
+    v[f].x = qx;
+    v[f].y = qy;
   }
 }
 template <int K, typename C>
 __device__ __forceinline__ void r1d(C* v, C d0, C d1) {
 #pragma unroll
-  for (int e = 0; e < NE; ++e) v[e] = cmul(v[e], (e >> K) & 1 ? d1 : d0);
+  for (int e = 0; e < NE; ++e) cmul_ip(v[e], (e >> K) & 1 ? d1 : d0);
 }
 template <int K, bool TWO, typename C>
 __device__ __forceinline__ void op1x(C* v, C* w, const C* __restrict__ mp) {
@@ -1129,8 +1204,8 @@ __device__ __forceinline__ void phase1(C* v, C* w, C F, bool wtriv, bool wscaled
       else wr = TWO ? cconj(qt[e]) : qt[e];
       fe = cmul(fe, wr);
     }
-    v[e] = cmul(v[e], fe);
-    if (TWO) w[e] = cmul(w[e], fe);
+    cmul_ip(v[e], fe);
+    if (TWO) cmul_ip(w[e], fe);
   }
 }
 
@@ -1515,8 +1590,8 @@ __device__ __forceinline__ void pass_body(
           const C F3 = cmul(EN(sr.rb[3]), B(4));
           auto apply = [&](int e, C fe) {
             if (!wtriv) fe = cmul(fe, TWO ? cconj(wc[e]) : wc[e]);
-            v[e] = cmul(v[e], fe);
-            if (TWO) w[e] = cmul(w[e], fe);
+            cmul_ip(v[e], fe);
+            if (TWO) cmul_ip(w[e], fe);
           };
           // Gray-code order with one running factor: each step sets a bit
           // (times F_k) or clears one (times conj F_k, |F_k| = 1)
@@ -1551,8 +1626,8 @@ __device__ __forceinline__ void pass_body(
           for (int e = 0; e < NE; ++e) {
             if (!((e >> KBS) & 1)) continue;
             const C fe = wtriv ? F : cmul(F, TWO ? cconj(wc[e]) : wc[e]);
-            v[e] = cmul(v[e], fe);
-            if (TWO) w[e] = cmul(w[e], fe);
+            cmul_ip(v[e], fe);
+            if (TWO) cmul_ip(w[e], fe);
           }
         };
         for (int oi = 0; oi < st.nops; ++oi) {
