@@ -706,10 +706,12 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
   }
   __syncthreads();
   double acc = 0.0;
+  const bool accum = WRITE && !ps.first;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     uint64_t base = (uint64_t)t << L;
     for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
-    for (int j = tid; j < M; j += kThreads) tile[j] = psi[base | hoff[j >> L] | (uint64_t)(j & lomask)];
+    auto gaddr = [&](int y) { return base | hoff[y >> L] | (uint64_t)(y & lomask); };
+    for (int j = tid; j < M; j += kThreads) tile[j] = psi[gaddr(j)];
     __syncthreads();
     R ar[EPT], ai[EPT];
 #pragma unroll
@@ -723,16 +725,38 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
         const R kr = (R)(T.ny4 == 0 ? c : T.ny4 == 2 ? -c : 0.0);
         const R ki = (R)(T.ny4 == 1 ? c : T.ny4 == 3 ? -c : 0.0);
         const uint32_t zl = T.zl;
+        if (zl == 0 && !(T.ny4 & 1)) {  // uniform: a real coefficient for the whole tile
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const int y = tid + e * kThreads;
-          if (y < M) {
-            const uint32_t x = (uint32_t)y ^ G.fl;
-            const C px = tile[x];
-            const bool neg = (__popc(x & zl) & 1) != 0;
-            const R sr = neg ? -kr : kr, si = neg ? -ki : ki;
-            ar[e] += sr * px.x - si * px.y;
-            ai[e] += sr * px.y + si * px.x;
+          for (int e = 0; e < EPT; ++e) {
+            const int y = tid + e * kThreads;
+            if (y < M) {
+              const C px = tile[(uint32_t)y ^ G.fl];
+              ar[e] += kr * px.x;
+              ai[e] += kr * px.y;
+            }
+          }
+        } else if (zl == 0) {  // an imaginary one
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const int y = tid + e * kThreads;
+            if (y < M) {
+              const C px = tile[(uint32_t)y ^ G.fl];
+              ar[e] -= ki * px.y;
+              ai[e] += ki * px.x;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const int y = tid + e * kThreads;
+            if (y < M) {
+              const uint32_t x = (uint32_t)y ^ G.fl;
+              const C px = tile[x];
+              const bool neg = (__popc(x & zl) & 1) != 0;
+              const R sr = neg ? -kr : kr, si = neg ? -ki : ki;
+              ar[e] += sr * px.x - si * px.y;
+              ai[e] += sr * px.y + si * px.x;
+            }
           }
         }
       }
@@ -743,13 +767,19 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
       if (y < M) {
         const C py = tile[y];
         acc += (double)py.x * ar[e] + (double)py.y * ai[e];
-        if (WRITE) {
-          const uint64_t ga = base | hoff[y >> L] | (uint64_t)(y & lomask);
-          if (ps.first) {
-            lam[ga] = mk<C>(ar[e], ai[e]);
-          } else {
+      }
+    }
+    if (WRITE) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int y = tid + e * kThreads;
+        if (y < M) {
+          const uint64_t ga = gaddr(y);
+          if (accum) {
             const C l = lam[ga];
             lam[ga] = mk<C>((double)l.x + ar[e], (double)l.y + ai[e]);
+          } else {
+            lam[ga] = mk<C>(ar[e], ai[e]);
           }
         }
       }
