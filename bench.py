@@ -144,6 +144,9 @@ def sweep(n: int, dt: str, only: str | None):
     for g in (2, 4, 8, 12):
         bits = [0, 1, 2, 3, 4, 5, n - 1, n - 2, n - 3, n - 4, n - 5, n - 6][:g]
         cases[f"pass_{g}_haar1q"] = [qsynth.gate("MAT", (Q(bt),), mat=hu(1)) for bt in bits]
+    bits12 = [0, 1, 2, 3, 4, 5, n - 1, n - 2, n - 3, n - 4, n - 5, n - 6]
+    cases["pass_12_ry_cz"] = ([qsynth.gate("RY", (Q(bt),), theta=0.3 + 0.1 * i) for i, bt in enumerate(bits12)]
+                              + [qsynth.gate("Z", (Q(a),), (Q(b),)) for a, b in zip(bits12, bits12[1:])])
     cases["swap_network"] = [qsynth.gate("SWAP", (j, n - 1 - j)) for j in range(n // 2)]
     mf = {}
     for k, tg in ((3, (0, 1, 2)), (4, (0, 1, 2, 3)), (5, (0, 1, 2, 3, 4)), (4, (n - 4, n - 3, n - 2, n - 1)),

@@ -387,6 +387,36 @@ def test_adjoint_variational_12q_vs_parameter_shift(api):
         assert np.max(np.abs(g - g_ps)) < tol, dt
 
 
+@pytest.mark.parametrize("n,dt,tol", [(24, "c128", 1e-9), (30, "c64", 2e-3)])
+def test_adjoint_full_size_vs_parameter_shift(api, n, dt, tol):
+    # beyond 23 qubits every workgroup of a pass walks several tiles: the
+    # two-state pass prefetches the next tile, gradient partials are summed
+    # over tiles and the phase tables take tile-index bits.  RY gates obey
+    # the parameter-shift rule exactly, dE/dt = (E(t + pi/2) - E(t - pi/2)) / 2,
+    # checked on sampled angles against the library's own energies
+    _, spec, params, terms = qsynth.gradient_20q(seed=4, n=n, layers=3)
+    banner("adjoint full size", n, dt)
+    c = api.Circuit.from_spec(n, spec)
+    H = api.Observable.pauli_sum(n, terms)
+    psi = api.State(n, dt)
+    lam = api.State(n, dt)
+    c.run(psi, params)
+    e_fwd = H.expectation(psi)
+    e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+    del lam
+    assert abs(e - e_fwd) < tol * max(1.0, abs(e_fwd))
+    rng = np.random.default_rng(n)
+    for k in rng.choice(c.nparams, 4, replace=False):
+        ep = []
+        for sgn in (1.0, -1.0):
+            p = params.copy()
+            p[k] += sgn * np.pi / 2
+            psi.set_basis(0)
+            c.run(psi, p)
+            ep.append(H.expectation(psi))
+        assert abs(g[k] - (ep[0] - ep[1]) / 2) < tol * max(1.0, abs(g[k])), (k, g[k], ep)
+
+
 def test_autograd_energy(api):
     import torch
     from paper_2009_01845_amd.autograd import energy
