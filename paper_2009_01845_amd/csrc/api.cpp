@@ -987,18 +987,21 @@ qs_status qs_sample(const qs_state* cs, int32_t m, const int32_t* qubits, int64_
         if (!(uniforms[j] >= 0.0 && uniforms[j] < 1.0)) fail(QS_E_INVALID, "uniforms must lie in [0, 1)");
     if (shots == 0) return;
     const int64_t nb = sample_nblocks(s->n);
-    // layout of scratch2: blocksums[nb] | prefix[nb+1] | uniforms[shots] | out[shots]
-    const size_t need = sizeof(double) * (2 * nb + 1 + (uniforms ? shots : 0)) + sizeof(int64_t) * shots + 64;
+    const int64_t nc = sample_nchunks(s->n);
+    // layout of scratch2: blocksums[nb] | prefix[nb+1] | chunks[2 nc + 1] | uniforms[shots] | out[shots]
+    const size_t need =
+        sizeof(double) * (2 * nb + 1 + 2 * nc + 1 + (uniforms ? shots : 0)) + sizeof(int64_t) * shots + 64;
     s->scratch2.ensure(need);
     double* bs = s->scratch2.as<double>();
     double* pre = bs + nb;
-    double* du = pre + nb + 1;
+    double* chunks = pre + nb + 1;
+    double* du = chunks + 2 * nc + 1;
     int64_t* dout = reinterpret_cast<int64_t*>(du + (uniforms ? shots : 0));
     if (uniforms)
       hipck(hipMemcpyAsync(du, uniforms, sizeof(double) * shots, hipMemcpyHostToDevice, s->stream), "uniforms");
     {
       ProfScope pr(6, s->stream);
-      hipck(launch_sample(s->dbl(), s->ptr, s->n, bs, pre, shots, seed, uniforms ? du : nullptr, pos.data(), m,
+      hipck(launch_sample(s->dbl(), s->ptr, s->n, bs, pre, chunks, shots, seed, uniforms ? du : nullptr, pos.data(), m,
                           dout, s->stream),
             "sample");
     }

@@ -138,11 +138,14 @@ hipError_t launch_slot_sums(const double* partials, int nslots, int nblocks, int
                             hipStream_t s);
 
 // Sampling (see qsim.h): block sums, scan, per-shot search.
-hipError_t launch_sample(bool dbl, const void* psi, int n, double* blocksums, double* prefix, int64_t shots,
-                         uint64_t seed, const double* uniforms, const int* pos, int m, int64_t* out,
+// blocksums: sample_nblocks(n) doubles; prefix: sample_nblocks(n) + 1; chunks:
+// 2 * sample_nchunks(n) + 1 (chunk totals and their prefix).
+hipError_t launch_sample(bool dbl, const void* psi, int n, double* blocksums, double* prefix, double* chunks,
+                         int64_t shots, uint64_t seed, const double* uniforms, const int* pos, int m, int64_t* out,
                          hipStream_t s);
 // zero `count` doubles with a kernel (graph-capture safe)
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 int sample_nblocks(int n);
+int sample_nchunks(int n);
 
 }  // namespace qs

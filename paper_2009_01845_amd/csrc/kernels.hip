@@ -844,6 +844,7 @@ __global__ __launch_bounds__(256) void k_slot_sums(const double* __restrict__ pa
 // ----------------------------------------------------------------------------
 constexpr int kSampBlock = 1024;
 constexpr int kSampPerLane = 16;
+constexpr int kSampChunk = 1024;  // block sums per chunk of the prefix scan
 
 // inclusive wave scan of lane sums in a fixed (Hillis-Steele) order
 __device__ __forceinline__ double wave_incl_scan(double v) {
@@ -869,14 +870,83 @@ __device__ __forceinline__ double lane_mass(const typename CT<R>::C* psi, int64_
   return s;
 }
 
+__device__ __forceinline__ double vec_mass(float4 v) {
+  return ((double)v.x * v.x + (double)v.y * v.y) + ((double)v.z * v.z + (double)v.w * v.w);
+}
+__device__ __forceinline__ double vec_mass(double2 v) { return v.x * v.x + v.y * v.y; }
+
+// one wave per block of kSampBlock amplitudes: the block's total mass from
+// coalesced 16-byte loads, summed in a fixed order (the shot search rebuilds
+// the block's split over lanes itself)
 template <typename R>
 __global__ __launch_bounds__(256) void k_samp_blocks(const typename CT<R>::C* __restrict__ psi, int64_t N,
                                                      int64_t nb, double* __restrict__ S) {
+  using V = typename CT<R>::V;
+  constexpr int VW = CT<R>::VW;
   const int64_t blk = blockIdx.x * (int64_t)(kThreads >> 6) + (threadIdx.x >> 6);
-  if (blk >= nb) return;
+  if (blk >= nb) return;  // uniform over the wave
   const int lane = threadIdx.x & 63;
-  const double incl = wave_incl_scan(lane_mass<R>(psi, N, blk, lane));
-  if (lane == 63) S[blk] = incl;
+  const int64_t first = blk * kSampBlock;
+  double s = 0.0;
+  if (first + kSampBlock <= N) {
+#pragma unroll
+    for (int e = 0; e < kSampBlock / (64 * VW); ++e)
+      s += vec_mass(*reinterpret_cast<const V*>(psi + first + (int64_t)(e * 64 + lane) * VW));
+  } else {
+    for (int64_t x = first + lane; x < N; x += 64) {
+      const auto v = psi[x];
+      s += (double)v.x * v.x + (double)v.y * v.y;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) S[blk] = s;
+}
+
+// block sums -> totals of chunks of kSampChunk blocks (fixed-order tree sum)
+__global__ __launch_bounds__(256) void k_samp_chunks(const double* __restrict__ S, int64_t nb,
+                                                     double* __restrict__ Ctot) {
+  __shared__ double red[8];
+  const int64_t c0 = blockIdx.x * (int64_t)kSampChunk;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSampChunk / kThreads; ++k) {
+    const int64_t i = c0 + k * kThreads + threadIdx.x;
+    if (i < nb) s += S[i];
+  }
+  const double r = block_sum(s, red);
+  if (threadIdx.x == 0) Ctot[blockIdx.x] = r;
+}
+
+// exclusive prefix of the block sums inside each chunk, offset by the chunk's
+// exclusive prefix Coff; P[nb] = Coff[nc], the total
+__global__ __launch_bounds__(256) void k_samp_prefix(const double* __restrict__ S, int64_t nb,
+                                                     const double* __restrict__ Coff, int64_t nc,
+                                                     double* __restrict__ P) {
+  constexpr int PT = kSampChunk / kThreads;  // consecutive blocks per thread
+  __shared__ double wsum[kThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t i0 = blockIdx.x * (int64_t)kSampChunk + (int64_t)tid * PT;
+  double v[PT];
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    v[k] = i0 + k < nb ? S[i0 + k] : 0.0;
+    t += v[k];
+  }
+  const double incl = wave_incl_scan(t);
+  double excl = __shfl_up(incl, 1, 64);
+  if (lane == 0) excl = 0.0;
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  double run = Coff[blockIdx.x];
+  for (int k = 0; k < w; ++k) run += wsum[k];
+  run += excl;
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    if (i0 + k < nb) P[i0 + k] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == 0 && tid == 0) P[nb] = Coff[nc];
 }
 
 // exclusive prefix of S into P[0..nb], one workgroup of 1024 threads
@@ -2458,17 +2528,30 @@ int sample_nblocks(int n) {
   return (int)((N + kSampBlock - 1) / kSampBlock);
 }
 
-hipError_t launch_sample(bool dbl, const void* psi, int n, double* blocksums, double* prefix, int64_t shots,
-                         uint64_t seed, const double* uniforms, const int* pos, int m, int64_t* out,
+int sample_nchunks(int n) { return (sample_nblocks(n) + kSampChunk - 1) / kSampChunk; }
+
+hipError_t launch_sample(bool dbl, const void* psi, int n, double* blocksums, double* prefix, double* chunks,
+                         int64_t shots, uint64_t seed, const double* uniforms, const int* pos, int m, int64_t* out,
                          hipStream_t s) {
   const int64_t N = 1ll << n;
   const int64_t nb = sample_nblocks(n);
+  const int64_t nc = sample_nchunks(n);
   const int g1 = (int)((nb + 3) / 4);
   if (dbl) hipLaunchKernelGGL((k_samp_blocks<double>), dim3(g1), dim3(256), 0, s, (const double2*)psi, N, nb, blocksums);
   else hipLaunchKernelGGL((k_samp_blocks<float>), dim3(g1), dim3(256), 0, s, (const float2*)psi, N, nb, blocksums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_samp_scan, dim3(1), dim3(1024), 0, s, blocksums, nb, prefix);
+  // prefix of the block sums: chunk totals, their exclusive prefix (one
+  // workgroup: at most 2^15 chunks), then each chunk's own prefix
+  double* ctot = chunks;
+  double* coff = chunks + nc;
+  hipLaunchKernelGGL(k_samp_chunks, dim3((unsigned)nc), dim3(kThreads), 0, s, blocksums, nb, ctot);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_samp_scan, dim3(1), dim3(1024), 0, s, ctot, nc, coff);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_samp_prefix, dim3((unsigned)nc), dim3(kThreads), 0, s, blocksums, nb, coff, nc, prefix);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (shots == 0) return hipSuccess;
