@@ -616,39 +616,57 @@ __global__ __launch_bounds__(256) void k_expect_poly(const typename CT<R>::C* __
                                                      typename CT<R>::C* __restrict__ out, int n,
                                                      const double* __restrict__ poly, const double* __restrict__ elo,
                                                      double* __restrict__ part) {
+  using C = typename CT<R>::C;
+  using V = typename CT<R>::V;
+  constexpr int VW = CT<R>::VW;
   constexpr int LB = 12;
+  constexpr int NV = (1 << LB) / (kThreads * VW);  // 16-byte vectors per thread in a full row
+  constexpr int NH = kMaxQubits - LB;              // row-index (high) bits at most
   __shared__ double sElo[1 << LB];
+  __shared__ double sLh[NH * NH];  // lam between high bits lb + i and lb + k
+  __shared__ double sLx[LB * NH];  // lam between row bit pb and high bit lb + k
+  __shared__ double sMu[NH];
   __shared__ double nu[LB];
   __shared__ double N1[64], N2[64];
   __shared__ double sA;
   __shared__ double red[8];
   const int tid = threadIdx.x;
   const int lb = n < LB ? n : LB;
+  const int nh = n - lb;
   const int rows = 1 << lb;
-  const int64_t ntiles = 1ll << (n - lb);
-  for (int j = tid; j < rows; j += kThreads) sElo[j] = elo[j];
+  const bool full = rows == (1 << LB);
+  const int64_t ntiles = 1ll << nh;
   const double* mu = poly + 1;
   const double* lam = poly + 1 + n;
+  // the coefficients every row's set-up reads, staged once
+  for (int j = tid; j < rows; j += kThreads) sElo[j] = elo[j];
+  for (int i = tid; i < nh * nh; i += kThreads) sLh[i] = lam[(lb + i / nh) * n + lb + i % nh];
+  for (int i = tid; i < lb * nh; i += kThreads) sLx[i] = lam[(i / nh) * n + lb + i % nh];
+  for (int i = tid; i < nh; i += kThreads) sMu[i] = mu[lb + i];
   double acc = 0.0;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t hbits = (uint64_t)t << lb;  // the row's high index bits
-    __syncthreads();                            // the previous row is done with nu, N1, N2, sA
+    V buf[NV];
+    if (full) {  // the row's loads are in flight during its set-up
+#pragma unroll
+      for (int u = 0; u < NV; ++u) buf[u] = *reinterpret_cast<const V*>(psi + hbits + (int64_t)(u * kThreads + tid) * VW);
+    }
+    __syncthreads();  // staged coefficients ready; the previous row is done with nu, N1, N2, sA
     if (tid < 64) {
-      // lane q < n - lb: the terms whose lowest set high bit is q; lanes 32..: nu
+      // lane i < nh: the terms whose lowest set high bit is lb + i; lanes 32..: nu
       double a = 0.0;
-      const int q = lb + tid;
-      if (tid < 32 && q < n && ((hbits >> q) & 1)) {
-        a = mu[q];
-        for (int r = q + 1; r < n; ++r)
-          if ((hbits >> r) & 1) a += lam[q * n + r];
+      if (tid < 32 && tid < nh && ((t >> tid) & 1)) {
+        a = sMu[tid];
+        for (int k = tid + 1; k < nh; ++k)
+          if ((t >> k) & 1) a += sLh[tid * nh + k];
       }
       for (int off = 16; off > 0; off >>= 1) a += __shfl_xor(a, off, 32);
       if (tid == 0) sA = poly[0] + a;
       if (tid >= 32 && tid - 32 < lb) {
         const int pb = tid - 32;
         double v = 0.0;
-        for (int r = lb; r < n; ++r)
-          if ((hbits >> r) & 1) v += lam[pb * n + r];
+        for (int k = 0; k < nh; ++k)
+          if ((t >> k) & 1) v += sLx[pb * nh + k];
         nu[pb] = v;
       }
     }
@@ -663,11 +681,41 @@ __global__ __launch_bounds__(256) void k_expect_poly(const typename CT<R>::C* __
     }
     __syncthreads();
     const double A = sA;
-    for (int j = tid; j < rows; j += kThreads) {
-      const auto v = psi[hbits | (uint64_t)j];
-      const double e = A + sElo[j] + N1[j & 63] + N2[j >> 6];
-      acc += ((double)v.x * v.x + (double)v.y * v.y) * e;
-      if (WRITE) out[hbits | (uint64_t)j] = mk<typename CT<R>::C>(e * v.x, e * v.y);
+    if (full) {
+#pragma unroll
+      for (int u = 0; u < NV; ++u) {
+        const int j0 = (u * kThreads + tid) * VW;
+        const V v = buf[u];
+        if constexpr (VW == 2) {
+          const double e0 = A + sElo[j0] + N1[j0 & 63] + N2[j0 >> 6];
+          const double e1 = A + sElo[j0 + 1] + N1[(j0 + 1) & 63] + N2[(j0 + 1) >> 6];
+          acc += ((double)v.x * v.x + (double)v.y * v.y) * e0 + ((double)v.z * v.z + (double)v.w * v.w) * e1;
+          if (WRITE) {
+            V o;
+            o.x = (R)(e0 * v.x);
+            o.y = (R)(e0 * v.y);
+            o.z = (R)(e1 * v.z);
+            o.w = (R)(e1 * v.w);
+            *reinterpret_cast<V*>(out + hbits + j0) = o;
+          }
+        } else {
+          const double e = A + sElo[j0] + N1[j0 & 63] + N2[j0 >> 6];
+          acc += ((double)v.x * v.x + (double)v.y * v.y) * e;
+          if (WRITE) {
+            V o;
+            o.x = (R)(e * v.x);
+            o.y = (R)(e * v.y);
+            *reinterpret_cast<V*>(out + hbits + j0) = o;
+          }
+        }
+      }
+    } else {
+      for (int j = tid; j < rows; j += kThreads) {
+        const auto v = psi[hbits | (uint64_t)j];
+        const double e = A + sElo[j] + N1[j & 63] + N2[j >> 6];
+        acc += ((double)v.x * v.x + (double)v.y * v.y) * e;
+        if (WRITE) out[hbits | (uint64_t)j] = mk<C>(e * v.x, e * v.y);
+      }
     }
   }
   const double r = block_sum(acc, red);
