@@ -759,7 +759,21 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
     uint64_t base = (uint64_t)t << L;
     for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
     auto gaddr = [&](int y) { return base | hoff[y >> L] | (uint64_t)(y & lomask); };
-    for (int j = tid; j < M; j += kThreads) tile[j] = psi[gaddr(j)];
+    if (sizeof(R) == 4 && M == EPT * kThreads) {
+      // a full complex64 tile: 16-byte loads, all in flight before the first
+      // LDS write (complex128 keeps the element loop: the buffer would cost it
+      // a wave per SIMD)
+      using V = typename CT<R>::V;
+      constexpr int VW = CT<R>::VW;
+      constexpr int NLD = EPT / VW;
+      V buf[NLD];
+#pragma unroll
+      for (int u = 0; u < NLD; ++u) buf[u] = *reinterpret_cast<const V*>(psi + gaddr((u * kThreads + tid) * VW));
+#pragma unroll
+      for (int u = 0; u < NLD; ++u) *reinterpret_cast<V*>(tile + (u * kThreads + tid) * VW) = buf[u];
+    } else {
+      for (int j = tid; j < M; j += kThreads) tile[j] = psi[gaddr(j)];
+    }
     __syncthreads();
     R ar[EPT], ai[EPT];
 #pragma unroll
