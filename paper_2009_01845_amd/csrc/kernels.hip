@@ -755,6 +755,11 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
   __syncthreads();
   double acc = 0.0;
   const bool accum = WRITE && !ps.first;
+  // element e of a thread: when a complex64 set writes lambda, threads own
+  // consecutive pairs (the layout of its 16-byte stores); otherwise a stride
+  // of kThreads (fewer registers)
+  constexpr bool PAIR = WRITE && sizeof(R) == 4;
+  auto yof = [&](int e) { return PAIR ? ((e >> 1) * kThreads + tid) * 2 + (e & 1) : tid + e * kThreads; };
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     uint64_t base = (uint64_t)t << L;
     for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
@@ -790,7 +795,7 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
         if (zl == 0 && !(T.ny4 & 1)) {  // uniform: a real coefficient for the whole tile
 #pragma unroll
           for (int e = 0; e < EPT; ++e) {
-            const int y = tid + e * kThreads;
+            const int y = yof(e);
             if (y < M) {
               const C px = tile[(uint32_t)y ^ G.fl];
               ar[e] += kr * px.x;
@@ -800,7 +805,7 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
         } else if (zl == 0) {  // an imaginary one
 #pragma unroll
           for (int e = 0; e < EPT; ++e) {
-            const int y = tid + e * kThreads;
+            const int y = yof(e);
             if (y < M) {
               const C px = tile[(uint32_t)y ^ G.fl];
               ar[e] -= ki * px.y;
@@ -810,7 +815,7 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
         } else {
 #pragma unroll
           for (int e = 0; e < EPT; ++e) {
-            const int y = tid + e * kThreads;
+            const int y = yof(e);
             if (y < M) {
               const uint32_t x = (uint32_t)y ^ G.fl;
               const C px = tile[x];
@@ -825,16 +830,49 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
     }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const int y = tid + e * kThreads;
+      const int y = yof(e);
       if (y < M) {
         const C py = tile[y];
         acc += (double)py.x * ar[e] + (double)py.y * ai[e];
       }
     }
-    if (WRITE) {
+    bool written = false;
+    if constexpr (PAIR) {
+      if (WRITE && M == EPT * kThreads) {
+      // lambda as 16-byte vectors: the old values of the set's tile in two
+      // batches of loads, then the sums
+      using V = typename CT<R>::V;
+#pragma unroll
+      for (int h = 0; h < EPT / 2; h += 4) {
+        V lv[4];
+        if (accum) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) lv[u] = *reinterpret_cast<const V*>(lam + gaddr(((h + u) * kThreads + tid) * 2));
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = 2 * (h + u);
+          V o;
+          o.x = ar[e];
+          o.y = ai[e];
+          o.z = ar[e + 1];
+          o.w = ai[e + 1];
+          if (accum) {
+            o.x = (R)((double)lv[u].x + ar[e]);
+            o.y = (R)((double)lv[u].y + ai[e]);
+            o.z = (R)((double)lv[u].z + ar[e + 1]);
+            o.w = (R)((double)lv[u].w + ai[e + 1]);
+          }
+          *reinterpret_cast<V*>(lam + gaddr(((h + u) * kThreads + tid) * 2)) = o;
+        }
+      }
+      written = true;
+      }
+    }
+    if (WRITE && !written) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        const int y = tid + e * kThreads;
+        const int y = yof(e);
         if (y < M) {
           const uint64_t ga = gaddr(y);
           if (accum) {
