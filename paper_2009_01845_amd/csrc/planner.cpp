@@ -415,37 +415,88 @@ void stage_pass(Plan& plan, Pass& ps) {
     std::vector<int> rb;
     std::vector<TileOp> ops;
   };
-  std::vector<St> sts;
-  St cur;
-  for (const TileOp& op : ps.ops) {
-    const std::vector<int> S = targets(op);
-    if (op.kind == OP_DENSEK) {  // slots 0..k-1 = targets, last target in slot 0
-      if (!cur.ops.empty()) sts.push_back(cur);
-      cur = St();
-      for (int t = op.k - 1; t >= 0; --t) cur.rb.push_back(op.b[t]);
-      cur.ops.push_back(op);
-      continue;
+  // Ops that commute may run in any order: pack them into as few register
+  // stages as the dependencies allow.  Per op: the tile bits it changes
+  // non-diagonally, the bits it only reads or multiplies by a phase
+  // (controls, diagonal targets, a phase polynomial's support) and the bits
+  // it needs in register slots.  Two ops depend on each other when one
+  // changes a bit non-diagonally that the other touches.
+  const int N = (int)ps.ops.size();
+  std::vector<uint32_t> nd(N, 0), dg(N, 0), tm(N, 0);
+  for (int i = 0; i < N; ++i) {
+    const TileOp& op = ps.ops[i];
+    uint32_t t = 0;
+    for (int b : targets(op)) t |= 1u << b;
+    tm[i] = t;
+    dg[i] = op.cin;
+    bool diagonal = op.kind == OP_ROT && op.pauli == 3;
+    if (op.kind == OP_DENSE1) {
+      const cd* M = plan.matpool.data() + op.mat;
+      diagonal = M[1] == 0.0 && M[2] == 0.0 && M[5] == 0.0 && M[6] == 0.0;
     }
-    bool in = true;
-    for (int b : S) in &= has(cur.rb, b);
-    if (in) {
-      cur.ops.push_back(op);
-      continue;
+    if (op.kind != OP_DENSE1 && op.kind != OP_DENSE2 && op.kind != OP_ROT && op.kind != OP_PHASE) {
+      nd[i] = (1u << g.m) - 1u;  // not modelled: ordered against every op
+    } else if (op.kind == OP_PHASE) {
+      const double* P = plan.dpool.data() + plan.phases[op.aux].dpool;
+      for (int b = 0; b < g.m; ++b) {
+        const int q = pos(b);
+        bool on = P[1 + q] != 0.0;
+        for (int r = 0; r < n && !on; ++r) on = P[1 + n + size_t(q) * n + r] != 0.0 || P[1 + n + size_t(r) * n + q] != 0.0;
+        if (on) dg[i] |= 1u << b;
+      }
+    } else if (diagonal) {
+      dg[i] |= t;
+    } else {
+      nd[i] = t;
     }
-    std::vector<int> u = cur.rb;
-    for (int b : S)
-      if (!has(u, b)) u.push_back(b);
-    if ((int)u.size() <= kRegBits) {
-      cur.rb = u;
-      cur.ops.push_back(op);
-      continue;
-    }
-    sts.push_back(cur);
-    cur = St();
-    cur.rb = S;
-    cur.ops.push_back(op);
   }
-  if (!cur.ops.empty()) sts.push_back(cur);
+  std::vector<std::vector<int>> pred(N);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < i; ++j)
+      if ((nd[j] & (nd[i] | dg[i])) || (nd[i] & (nd[j] | dg[j]))) pred[i].push_back(j);
+  std::vector<char> done(N, 0);
+  auto ready = [&](int i) {
+    if (done[i]) return false;
+    for (int j : pred[i])
+      if (!done[j]) return false;
+    return true;
+  };
+  std::vector<St> sts;
+  int left = N;
+  while (left > 0) {
+    St cur;
+    uint32_t mask = 0;
+    auto take = [&](int i) {
+      for (int b : targets(ps.ops[i]))
+        if (!has(cur.rb, b)) cur.rb.push_back(b);
+      mask |= tm[i];
+      cur.ops.push_back(ps.ops[i]);
+      done[i] = 1;
+      --left;
+    };
+    for (;;) {
+      bool grew = false;
+      for (int i = 0; i < N; ++i)  // every ready op that needs no new register bit, in order
+        if (ready(i) && (tm[i] & ~mask) == 0) {
+          take(i);
+          grew = true;
+        }
+      if (grew) continue;
+      int best = -1, bestnew = kRegBits + 1;  // else the ready op adding the fewest bits
+      for (int i = 0; i < N; ++i)
+        if (ready(i) && __builtin_popcount(mask | tm[i]) <= kRegBits) {
+          const int nb = __builtin_popcount(tm[i] & ~mask);
+          if (nb < bestnew) {
+            bestnew = nb;
+            best = i;
+          }
+        }
+      if (best < 0) break;
+      take(best);
+    }
+    if (cur.ops.empty()) throw std::runtime_error("planner: no op fits a register stage");
+    sts.push_back(cur);
+  }
 
   std::vector<TileOp> out;
   g.st0 = (int)plan.stages.size();
