@@ -190,14 +190,14 @@ def test_sign_only_phases_ry_cz_ring(api, dt):
     c.run(st, params)
     ref = ocirc.run(n, spec, None, params)
     assert maxabs(st.download(), ref) < TOL[dt]
-    if dt == "c128":
-        from oracle import gradients as ograd
-        psi, lam = api.State(n, dt), api.State(n, dt)
-        c.run(psi, params)
-        H = api.Observable.pauli_sum(n, terms)
-        e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
-        e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
-        assert abs(e - e_ref) < 1e-10 and np.max(np.abs(g - g_ref)) < 1e-10
+    from oracle import gradients as ograd
+    gtol = 1e-10 if dt == "c128" else 1e-4
+    psi, lam = api.State(n, dt), api.State(n, dt)
+    c.run(psi, params)
+    H = api.Observable.pauli_sum(n, terms)
+    e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+    e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+    assert abs(e - e_ref) < gtol and np.max(np.abs(g - g_ref)) < gtol
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -244,16 +244,16 @@ def test_pauli_tile_sets_expectation_and_adjoint(api, dt):
     for terms in (mixed, only_x):
         H = api.Observable.pauli_sum(n, terms)
         assert abs(H.expectation(st) - oobs.expectation(ref, terms).real) < tol * 10
-    if dt == "c128":
-        _, spec, params, _ = qsynth.gradient_20q(seed=3, n=n, layers=2)
-        c = api.Circuit.from_spec(n, spec)
-        for terms in (mixed, only_x):
-            psi, lam = api.State(n, dt), api.State(n, dt)
-            c.run(psi, params)
-            H = api.Observable.pauli_sum(n, terms)
-            e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
-            e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
-            assert abs(e - e_ref) < 1e-10 and np.max(np.abs(g - g_ref)) < 1e-10
+    gtol = 1e-10 if dt == "c128" else 1e-3  # complex64: 40 terms of |c| ~ 1
+    _, spec, params, _ = qsynth.gradient_20q(seed=3, n=n, layers=2)
+    c = api.Circuit.from_spec(n, spec)
+    for terms in (mixed, only_x):
+        psi, lam = api.State(n, dt), api.State(n, dt)
+        c.run(psi, params)
+        H = api.Observable.pauli_sum(n, terms)
+        e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+        e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+        assert abs(e - e_ref) < gtol and np.max(np.abs(g - g_ref)) < gtol
 
 
 # ---------------------------------------------------------------- sampling
