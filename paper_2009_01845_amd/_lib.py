@@ -83,6 +83,10 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2009_01845_amd.build`")
+        # torch ships its own HIP runtime; loading it first makes the library
+        # bind to that same runtime (a second copy, loaded from the system
+        # ROCm, would not see the device that torch has opened)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
