@@ -1551,8 +1551,12 @@ __device__ __forceinline__ void pass_body(
   using VT = typename CT<R>::V;
   constexpr int VW = CT<R>::VW;
   const int M = 1 << g.m;
+  // complex64 two-state passes without controls pass both states through one
+  // LDS tile in turn (SEQ): 41 KB per workgroup instead of 74 KB, three
+  // workgroups per CU instead of two, for three more barriers per stage
+  constexpr bool SEQ = TWO && !GUARD && !CTRL && sizeof(R) == 4 && NLD == 8;  // 12-bit tiles: one group per thread
   C* t1 = reinterpret_cast<C*>(smem);
-  C* t2 = TWO ? t1 + M : nullptr;
+  C* t2 = TWO && !SEQ ? t1 + M : nullptr;
   uint64_t* hoff = sm.hoff;
   auto& phA = sm.phA;
   auto& phNu = sm.phNu;
@@ -1636,7 +1640,7 @@ __device__ __forceinline__ void pass_body(
   // too few to hide the loads behind another workgroup's arithmetic: it
   // loads the next tile into registers while the current one is processed
   // (not in the variant with controls, whose registers are already full)
-  constexpr bool PF = TWO && !GUARD && !CTRL;
+  constexpr bool PF = TWO && !GUARD && !CTRL && !SEQ;
   using NV = typename CT<R>::NV;  // native vector: stays in registers when indexed
   NV pre[PF ? 2 * NLD : 1];
 #define QS_PREFETCH(TT)                                                                     \
@@ -1646,6 +1650,24 @@ __device__ __forceinline__ void pass_body(
     _Pragma("unroll") for (int u = 0; u < NLD; ++u) pre[NLD + u] = *reinterpret_cast<const NV*>(lam + gaddr(pb, u)); \
   }
   if (PF && t_first < ntiles) QS_PREFETCH(t_first);
+  NV seqb[SEQ ? NLD : 1], seql[SEQ ? NLD : 1];  // SEQ: the tile's two states on their way in
+  C v[NE], w[NE];  // a stage's register elements (SEQ keeps w from stage to stage)
+  // walk the register elements of stage s (LDS byte offsets, Gray order)
+  auto lds_walk = [&](const StageRec& sr, auto&& fn) {
+    constexpr uint32_t CBw = sizeof(C) == 8 ? 3 : 4;
+    const uint32_t i0 = swz<R>(1u << sr.rb[0]) << CBw, i1 = swz<R>(1u << sr.rb[1]) << CBw;
+    const uint32_t i2 = swz<R>(1u << sr.rb[2]) << CBw, i3 = swz<R>(1u << sr.rb[3]) << CBw;
+    uint32_t ad = swz<R>(insert_zeros((uint32_t)tid, sr.rbmask)) << CBw;
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      if (i) {
+        const int fb = __builtin_ctz(i);
+        ad ^= fb == 0 ? i0 : fb == 1 ? i1 : fb == 2 ? i2 : i3;
+        asm volatile("" : "+v"(ad));
+      }
+      fn(ad, i ^ (i >> 1));
+    }
+  };
 
   for (int64_t t = t_first; t < ntiles; t += t_step) {
     const uint64_t base = tbase(t);
@@ -1656,6 +1678,11 @@ __device__ __forceinline__ void pass_body(
         *reinterpret_cast<NV*>(t1 + e) = pre[u];
         *reinterpret_cast<NV*>(t2 + e) = pre[NLD + u];
       }
+    } else if (SEQ) {
+#pragma unroll
+      for (int u = 0; u < NLD; ++u) seqb[u] = *reinterpret_cast<const NV*>(psi + gaddr(base, u));
+#pragma unroll
+      for (int u = 0; u < NLD; ++u) *reinterpret_cast<NV*>(t1 + swz<R>((u * kThreads + tid) * VW)) = seqb[u];
     } else {
       for (int half = 0; half < (TWO ? 2 : 1); ++half) {
         const C* src = half ? lam : psi;
@@ -1729,7 +1756,6 @@ __device__ __forceinline__ void pass_body(
         const uint32_t jg = valid ? insert_zeros((uint32_t)(gb + tid), st.rbmask) : 0u;
         const int grp = valid ? gb + tid : 0;  // per-group table row (threads past the tile read row 0)
         uint32_t A = swz<R>(jg) << CB;
-        C v[NE], w[NE];
         {
           uint32_t ad = A;
 #pragma unroll
@@ -1737,8 +1763,21 @@ __device__ __forceinline__ void pass_body(
             if (i) step(ad, i);
             const int e = i ^ (i >> 1);
             v[e] = *reinterpret_cast<const C*>(b1 + ad);
-            if (TWO) w[e] = *reinterpret_cast<const C*>(b2 + ad);
+            if (TWO && !SEQ) w[e] = *reinterpret_cast<const C*>(b2 + ad);
           }
+        }
+        if (SEQ) {  // lambda through the buffer psi has just left
+          __syncthreads();
+          if (si == 0) {  // lambda's tile arrives now: fewer registers live across the set-up
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) seql[u] = *reinterpret_cast<const NV*>(lam + gaddr(base, u));
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) *reinterpret_cast<NV*>(t1 + swz<R>((u * kThreads + tid) * VW)) = seql[u];
+          } else {
+            lds_walk(stages[st0 + (nst - si)], [&](uint32_t ad, int e) { *reinterpret_cast<C*>(b1 + ad) = w[e]; });
+          }
+          __syncthreads();
+          lds_walk(st, [&](uint32_t ad, int e) { w[e] = *reinterpret_cast<const C*>(b1 + ad); });
         }
         // an empty asm that "redefines" A: the scatter recomputes its
         // addresses instead of keeping sixteen of them live across the ops
@@ -1921,6 +1960,7 @@ __device__ __forceinline__ void pass_body(
             if (TWO) r2_any(w, ops[o].b[0], ops[o].b[1], mp, creg);
           }
         }
+        if (SEQ) __syncthreads();  // every thread has read its lambda from the buffer
         if (valid) {
           uint32_t ad = A;
 #pragma unroll
@@ -1928,7 +1968,7 @@ __device__ __forceinline__ void pass_body(
             if (i) step(ad, i);
             const int e = i ^ (i >> 1);
             *reinterpret_cast<C*>(b1 + ad) = v[e];
-            if (TWO) *reinterpret_cast<C*>(b2 + ad) = w[e];
+            if (TWO && !SEQ) *reinterpret_cast<C*>(b2 + ad) = w[e];
           }
         }
       }
@@ -1938,7 +1978,12 @@ __device__ __forceinline__ void pass_body(
 
     for (int half = 0; half < (TWO ? 2 : 1); ++half) {
       C* dstg = half ? lam : psi;
-      const C* src = half ? t2 : t1;
+      const C* src = half && !SEQ ? t2 : t1;
+      if (SEQ && half) {  // lambda's last stage registers into the buffer psi has left
+        __syncthreads();
+        lds_walk(stages[st0], [&](uint32_t ad, int e) { *reinterpret_cast<C*>(reinterpret_cast<char*>(t1) + ad) = w[e]; });
+        __syncthreads();
+      }
       VT buf[NLD];
 #pragma unroll
       for (int u = 0; u < NLD; ++u)
@@ -2332,10 +2377,13 @@ hipError_t launch_tile_pass(bool dbl, void* psi, void* psi2, const PassGeom& g, 
   const int grid = tile_grid(g);
   const size_t esz = dbl ? 16 : 8;
   const bool two = psi2 != nullptr;
-  const size_t lds = (size_t(1) << g.m) * esz * (two ? 2 : 1);
+  size_t lds = (size_t(1) << g.m) * esz * (two ? 2 : 1);
   if (g.kern == 2) {
     if (g.m < 12 || g.nst < 1 || g.nph < 0 || g.nph > kMaxPhasePerPass) return hipErrorInvalidValue;
     const int nld = (1 << g.m) / (kThreads * (dbl ? 1 : 2));
+    // complex64 two-state passes of 12-bit tiles without controls hold one
+    // tile in LDS and pass the two states through it in turn
+    if (two && !dbl && !g.ctrl && nld == 8) lds = (size_t(1) << g.m) * esz;
     if (dbl && nld == 16) return launch_tile2_t<double, 16>(psi, psi2, g, dp, params, scales, gpart, nt, grid, lds, s);
     if (!dbl && nld == 8) return launch_tile2_t<float, 8>(psi, psi2, g, dp, params, scales, gpart, nt, grid, lds, s);
     if (!dbl && nld == 16) return launch_tile2_t<float, 16>(psi, psi2, g, dp, params, scales, gpart, nt, grid, lds, s);
