@@ -1026,16 +1026,20 @@ qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, i
     const bool dbl = s->dbl();
     PhasePoly E = ising_poly(n, h1->J.data(), h1->h.data());
     // blocks of S steps share passes (the last pass of a step carries the next
-    // step's rotations on its tile bits); then the remainder and the last layer
-    const int S = (int)std::min<int64_t>(K, 8);
-    const int64_t nblk = K / S, rem = K % S;
-    Plan block = plan_trotter(n, dbl, TuneOpts{}, &E, S);
-    Plan tail;
-    if (rem) tail = plan_trotter(n, dbl, TuneOpts{}, &E, (int)rem);
-    Plan last = plan_rx_layer(n, dbl, TuneOpts{}, nullptr);
-    DevPlanBuf dblock, dtail, dlast;
-    dblock.load(block, s->stream);
-    if (rem) dtail.load(tail, s->stream);
+    // step's rotations on its tile bits).  Up to 16 steps form one block; longer
+    // runs replay blocks of 8.  The last segment (the final block or the
+    // remainder) also carries the closing half rotation layer.
+    const int S = (int)(K <= 16 ? K : 8);
+    const int64_t rem = K % S;
+    const int64_t nfull = K / S - (rem ? 0 : 1);  // blocks before the last segment
+    const int L = (int)(rem ? rem : S);           // steps of the last segment
+    Plan block, last;
+    DevPlanBuf dblock, dlast;
+    if (nfull > 0) {
+      block = plan_trotter(n, dbl, TuneOpts{}, &E, S);
+      dblock.load(block, s->stream);
+    }
+    last = plan_trotter(n, dbl, TuneOpts{}, &E, L, true);
     dlast.load(last, s->stream);
     // merged RX angles and phase scales
     std::vector<double> ang(K + 1), scl(K);
@@ -1050,13 +1054,12 @@ qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, i
     DBuf dang, dscl;
     upload(dang, ang, s->stream);
     upload(dscl, scl, s->stream);
-    for (int64_t b = 0; b < nblk; ++b)
+    for (int64_t b = 0; b < nfull; ++b)
       run_passes(dblock, block, dbl, s->ptr, nullptr, dang.as<double>() + b * S, dscl.as<double>() + b * S, nullptr,
                  s->stream);
-    if (rem)
-      run_passes(dtail, tail, dbl, s->ptr, nullptr, dang.as<double>() + nblk * S, dscl.as<double>() + nblk * S,
-                 nullptr, s->stream);
-    run_passes(dlast, last, dbl, s->ptr, nullptr, dang.as<double>() + K, nullptr, nullptr, s->stream);
+    // the last segment: angle slots K - L .. K (the closing layer is slot L), scales K - L .. K - 1
+    run_passes(dlast, last, dbl, s->ptr, nullptr, dang.as<double>() + (K - L), dscl.as<double>() + (K - L), nullptr,
+               s->stream);
     if (energy_out) {
       auto* o = const_cast<qs_obs*>(h1);
       const int ng = (int)o->flips.size();

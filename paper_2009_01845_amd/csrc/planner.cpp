@@ -1193,27 +1193,10 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
   return plan;
 }
 
-Plan plan_rx_layer(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly) {
+Plan plan_trotter(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly, int steps, bool final_layer) {
   HostCircuit hc;
   hc.n = n;
-  hc.nparams = 1;
-  for (int q = 0; q < n; ++q) {
-    Gate g;
-    g.k = 1;
-    g.tq[0] = q;
-    g.is_rot = true;
-    g.pauli = 'X';
-    g.pidx = 0;
-    hc.gates.push_back(g);
-  }
-  hc.tail_phase = poly;
-  return plan_circuit(hc, opts, dbl);
-}
-
-Plan plan_trotter(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly, int steps) {
-  HostCircuit hc;
-  hc.n = n;
-  hc.nparams = steps;
+  hc.nparams = steps + (final_layer ? 1 : 0);
   for (int s = 0; s < steps; ++s) {
     for (int q = 0; q < n; ++q) {
       Gate g;
@@ -1229,6 +1212,16 @@ Plan plan_trotter(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly, 
     ph.scale_slot = s;
     hc.gates.push_back(ph);
   }
+  if (final_layer)  // the closing half rotation layer, angle slot `steps`, planned with the last steps
+    for (int q = 0; q < n; ++q) {
+      Gate g;
+      g.k = 1;
+      g.tq[0] = q;
+      g.is_rot = true;
+      g.pauli = 'X';
+      g.pidx = steps;
+      hc.gates.push_back(g);
+    }
   return plan_circuit(hc, opts, dbl);
 }
 

@@ -109,11 +109,11 @@ void default_tile(int n, bool dbl, const TuneOpts& o, int* m, int* L);
 TileOp make_phase_op(Plan& plan, const PassGeom& g, const PhasePoly& P, int scale_idx);
 // Ising energy E(z) as a polynomial in the index bits.
 PhasePoly ising_poly(int n, const double* J, const double* h);
-// RX(params[0]) on every qubit, optionally followed by exp(i scales[0] E(x)).
-Plan plan_rx_layer(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly);
 // `steps` Trotter steps in one plan: for s = 0..steps-1, RX(params[s]) on every
-// qubit then exp(i scales[s] E(x)); consecutive steps share passes.
-Plan plan_trotter(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly, int steps);
+// qubit then exp(i scales[s] E(x)); consecutive steps share passes.  With
+// final_layer, RX(params[steps]) on every qubit closes the plan.
+Plan plan_trotter(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly, int steps,
+                  bool final_layer = false);
 
 // Greedy fusion of consecutive fixed gates into blocks of at most K qubits.
 std::vector<Gate> fuse_gates(const std::vector<Gate>& in, int K);

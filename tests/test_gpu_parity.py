@@ -330,6 +330,25 @@ def test_adiabatic_trotter_staged_blocks(api, dt):
     assert abs(e - oad.energy(ref, E)) < (1e-10 if dt == "c128" else 1e-4)
 
 
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("steps", [10, 16, 32])
+def test_adiabatic_block_boundaries(api, dt, steps):
+    # up to 16 steps run as one block; 32 = four blocks of 8 with no remainder.
+    # Either way the last segment carries the closing half rotation layer
+    n = 13
+    banner("adiabatic blocks", dt, steps)
+    J, h = qsynth.ising_couplings(n, 9)
+    E = oobs.ising_energies(J, h)
+    T = steps * 0.01
+    ref = oad.trotter(n, E, T, 0.01)
+    st = api.State(n, dt)
+    st.set_plus()
+    I = api.Observable.ising(n, J, h)
+    e = api.adiabatic_run(st.h, I.h, T, 0.01)
+    assert maxabs(st.download(), ref) < (1e-11 if dt == "c128" else 2e-5)
+    assert abs(e - oad.energy(ref, E)) < (1e-10 if dt == "c128" else 1e-4)
+
+
 def test_adiabatic_j0_factorised_20q(api):
     n = 20
     banner("adiabatic J=0", n)
