@@ -276,6 +276,25 @@ def test_sampling_shared_uniforms(api, dt, shots):
             assert np.all(osamp.boundary_distance(ref, u[bad], idx) < 1e-6), bad
 
 
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("n", [7, 22])
+def test_sampling_block_and_chunk_edges(api, dt, n):
+    # n = 7: one block shorter than a block (128 of 1024 amplitudes); n = 22:
+    # 4096 block sums, a prefix over four chunks of 1024
+    banner("sampling edges", dt, n)
+    psi0 = qsynth.random_state(n, 40 + n)
+    st = gpu_state(api, n, dt, psi0)
+    ref = oracle_input(psi0, dt)
+    u = np.random.default_rng(n).random(2000)
+    for qubits in (list(range(n)), [n - 1, 0]):
+        got = api.sample(st.h, qubits, len(u), uniforms=u)
+        exp = osamp.sample(ref, qubits, u)
+        bad = np.nonzero(got != exp)[0]
+        if bad.size:
+            idx = osamp.sample_indices(ref, u[bad])
+            assert np.all(osamp.boundary_distance(ref, u[bad], idx) < 1e-6), bad
+
+
 def test_sampling_philox_seed_mode_matches_oracle_generator(api):
     n = 12
     banner("sampling philox")
