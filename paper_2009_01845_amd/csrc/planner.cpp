@@ -10,7 +10,9 @@
 //     element-wise, deferred until a non-diagonal gate touches one of its bits.
 //  3. The other gates are scheduled greedily, in dependency order, into tiled
 //     passes: the tile bit set T = {0..L-1} U (up to m-L high bits); a gate
-//     joins the open pass when its targets fit in T.
+//     joins the open pass when its targets fit in T.  The high bits are those
+//     the first gates in index order ask for, or are picked ahead by how many
+//     gates they unlock; the plan with fewer passes is kept.
 #include "planner.h"
 
 #include <algorithm>
@@ -946,13 +948,13 @@ void add_perm_pass(Plan& plan, int n, int L, bool dbl, const std::vector<int>& t
 
 Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
   const int n = C.n;
-  Plan plan;
-  plan.n = n;
-  plan.dbl = dbl;
-  plan.nparams = C.nparams;
-  plan.ngates = (int)C.gates.size();
-  plan.grid_bits = opts.grid_bits;
-  plan.force_stage = opts.force_stage;
+  Plan proto;
+  proto.n = n;
+  proto.dbl = dbl;
+  proto.nparams = C.nparams;
+  proto.ngates = (int)C.gates.size();
+  proto.grid_bits = opts.grid_bits;
+  proto.force_stage = opts.force_stage;
   int m, L;
   default_tile(n, dbl, opts, &m, &L);
   const int Hmax = m - L;
@@ -978,7 +980,7 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
   // 2. dependency graph: two gates commute on a shared bit only when both act
   //    diagonally there (controls, diagonal gates, Z rotations)
   std::vector<std::vector<int>> succ(G);
-  std::vector<int> indeg(G, 0);
+  std::vector<int> indeg0(G, 0);
   {
     std::vector<int> lastN(n, -1);
     std::vector<std::vector<int>> dsince(n);
@@ -988,7 +990,7 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
         if (from < 0 || mark[from] == g) return;
         mark[from] = g;
         succ[from].push_back(g);
-        indeg[g]++;
+        indeg0[g]++;
       };
       uint64_t all = bg[g].nmask | bg[g].dmask;
       for (uint64_t t = all; t; t &= t - 1) {
@@ -1009,186 +1011,265 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
     }
   }
 
-  // 3. greedy list scheduling into tiled passes
-  std::set<int> ready;
-  for (int g = 0; g < G; ++g)
-    if (indeg[g] == 0) ready.insert(g);
-  PhasePoly P;
-  P.init(n);
-  std::set<int> hsel;
-  std::vector<RawOp> raw;
-  int scheduled = 0;
-  const uint64_t lowmask = L >= 64 ? ~0ull : ((1ull << L) - 1);
-  const bool fuse1 = opts.fuse_k != 1;
+  // 3. greedy list scheduling into tiled passes.  With lookahead, each pass
+  //    first picks its high bits: starting from the low bits, it repeatedly
+  //    adds the new bits of the blocked gate that unlock the most gates per
+  //    added bit (the gates reachable in dependency order inside the tile);
+  //    then gates are placed in index order as without lookahead.
+  auto schedule = [&](bool lookahead) -> Plan {
+    Plan plan = proto;
+    std::vector<int> indeg = indeg0;
+    std::set<int> ready;
+    for (int g = 0; g < G; ++g)
+      if (indeg[g] == 0) ready.insert(g);
+    PhasePoly P;
+    P.init(n);
+    std::set<int> hsel;
+    std::vector<RawOp> raw;
+    int scheduled = 0;
+    const uint64_t lowmask = L >= 64 ? ~0ull : ((1ull << L) - 1);
+    const bool fuse1 = opts.fuse_k != 1;
 
-  auto finish = [&](int g, std::set<int>::iterator& it) {
-    it = ready.erase(it);
-    ++scheduled;
-    for (int s : succ[g])
-      if (--indeg[s] == 0) ready.insert(s);
-  };
+    auto finish = [&](int g, std::set<int>::iterator& it) {
+      it = ready.erase(it);
+      ++scheduled;
+      for (int s : succ[g])
+        if (--indeg[s] == 0) ready.insert(s);
+    };
 
-  while (scheduled < G) {
-    bool progress = true;
-    int placed = 0;
-    while (progress) {
-      progress = false;
-      for (auto it = ready.begin(); it != ready.end();) {
-        const int g = *it;
-        BitGate& b = bg[g];
-        if (b.kind == BK_PHASE) {
-          add_terms(P, n, b);
-          finish(g, it);
-          progress = true;
-          ++placed;
-          continue;
+    std::vector<int> seen(G, 0), touched;
+    // non-phase gates placeable with tile bits T from the current ready set; the
+    // blocked gates that wait only for tile bits go to front
+    auto closure = [&](uint64_t T, std::vector<int>* front) {
+      std::vector<int> stack(ready.begin(), ready.end());
+      int cnt = 0, ngr = 0;
+      while (!stack.empty()) {
+        const int g = stack.back();
+        stack.pop_back();
+        const BitGate& b = bg[g];
+        const bool diag = b.kind == BK_PHASE || b.kind == BK_SPHASE;
+        if (!diag) {
+          if (b.mfma) continue;
+          bool fits = true;
+          for (int t = 0; t < b.k; ++t) fits = fits && ((T >> b.tb[t]) & 1);
+          if (!fits) {
+            if (front) front->push_back(g);
+            continue;
+          }
+          if (b.kind == BK_ROT && b.pidx >= 0 && ngr++ >= kMaxGradPerPass) continue;
+          ++cnt;
         }
-        if (b.kind == BK_SPHASE) {  // its own phase op, scaled per launch
-          if (nphase_raw(raw) >= kMaxPhasePerPass - 2) {
+        for (int s : succ[g]) {
+          if (seen[s]++ == 0) touched.push_back(s);
+          if (seen[s] == indeg[s]) stack.push_back(s);
+        }
+      }
+      for (int s : touched) seen[s] = 0;
+      touched.clear();
+      return cnt;
+    };
+    auto pick_bits = [&]() {
+      uint64_t T = lowmask;
+      int nh = 0;
+      std::vector<int> front;
+      std::vector<uint64_t> tried;
+      while (nh < Hmax) {
+        front.clear();
+        tried.clear();
+        const int base = closure(T, &front);
+        std::sort(front.begin(), front.end());
+        double best = 0.0;
+        uint64_t pick = 0;
+        for (int g : front) {
+          uint64_t need = 0;
+          for (int t = 0; t < bg[g].k; ++t) need |= (1ull << bg[g].tb[t]) & ~T;
+          const int c = __builtin_popcountll(need);
+          if (nh + c > Hmax || std::find(tried.begin(), tried.end(), need) != tried.end()) continue;
+          tried.push_back(need);
+          const double score = (double)(closure(T | need, nullptr) - base) / c;
+          if (score > best) {
+            best = score;
+            pick = need;
+          }
+        }
+        if (!pick) break;
+        T |= pick;
+        nh += __builtin_popcountll(pick);
+      }
+      for (uint64_t h = T & ~lowmask; h; h &= h - 1) hsel.insert(__builtin_ctzll(h));
+    };
+
+    while (scheduled < G) {
+      if (lookahead && hsel.empty()) pick_bits();
+      bool progress = true;
+      int placed = 0;
+      while (progress) {
+        progress = false;
+        for (auto it = ready.begin(); it != ready.end();) {
+          const int g = *it;
+          BitGate& b = bg[g];
+          if (b.kind == BK_PHASE) {
+            add_terms(P, n, b);
+            finish(g, it);
+            progress = true;
+            ++placed;
+            continue;
+          }
+          if (b.kind == BK_SPHASE) {  // its own phase op, scaled per launch
+            if (nphase_raw(raw) >= kMaxPhasePerPass - 2) {
+              ++it;
+              continue;
+            }
+            RawOp ro;
+            ro.kind = OP_PHASE;
+            ro.poly = *b.spoly;
+            ro.scale_idx = b.scale_slot;
+            raw.push_back(std::move(ro));
+            finish(g, it);
+            progress = true;
+            ++placed;
+            continue;
+          }
+          if (b.mfma) {  // placed between tiled passes below
             ++it;
             continue;
           }
-          RawOp ro;
-          ro.kind = OP_PHASE;
-          ro.poly = *b.spoly;
-          ro.scale_idx = b.scale_slot;
-          raw.push_back(std::move(ro));
+          std::vector<int> need;
+          for (int t = 0; t < b.k; ++t) {
+            int bit = b.tb[t];
+            if (!((lowmask >> bit) & 1) && !hsel.count(bit)) need.push_back(bit);
+          }
+          if ((int)(hsel.size() + need.size()) > Hmax) {
+            ++it;
+            continue;
+          }
+          if (b.nmask && nphase_raw(raw) >= kMaxPhasePerPass - 2) {  // keep the pass staged
+            ++it;
+            continue;
+          }
+          if (b.kind == BK_ROT && b.pidx >= 0 && ngrad_raw(raw) >= kMaxGradPerPass) {
+            ++it;
+            continue;
+          }
+          for (int bit : need) hsel.insert(bit);
+          if (b.nmask && (b.nmask & P.support())) {
+            // every pending term comes from a diagonal gate whose predecessors
+            // are all placed, so applying all of them here is exact and leaves
+            // fewer, fuller phase ops than flushing only the gate's bits
+            PhasePoly Q = extract_terms(P, n, ~0ull, false);
+            if (!Q.empty) {
+              RawOp ro;
+              ro.kind = OP_PHASE;
+              ro.poly = std::move(Q);
+              raw.push_back(std::move(ro));
+            }
+          }
+          const int kind = b.kind == BK_ROT ? OP_ROT : (b.k == 1 ? OP_DENSE1 : b.k == 2 ? OP_DENSE2 : OP_DENSEK);
+          bool merged = false;
+          if (fuse1 && kind == OP_DENSE1 && !raw.empty()) {
+            RawOp& last = raw.back();
+            if (last.kind == OP_DENSE1 && last.g.tb[0] == b.tb[0] && last.g.cmask == b.cmask) {
+              last.g.mat = matmul(b.mat, last.g.mat, 2);
+              merged = true;
+            }
+          }
+          if (!merged) {
+            RawOp ro;
+            ro.kind = kind;
+            ro.g = b;
+            raw.push_back(std::move(ro));
+          }
           finish(g, it);
           progress = true;
           ++placed;
-          continue;
         }
-        if (b.mfma) {  // placed between tiled passes below
-          ++it;
-          continue;
+      }
+      int mg = -1;  // a ready matrix-core block goes next, after this pass
+      for (int g : ready)
+        if (bg[g].mfma) {
+          mg = g;
+          break;
         }
-        std::vector<int> need;
-        for (int t = 0; t < b.k; ++t) {
-          int bit = b.tb[t];
-          if (!((lowmask >> bit) & 1) && !hsel.count(bit)) need.push_back(bit);
-        }
-        if ((int)(hsel.size() + need.size()) > Hmax) {
-          ++it;
-          continue;
-        }
-        if (b.nmask && nphase_raw(raw) >= kMaxPhasePerPass - 2) {  // keep the pass staged
-          ++it;
-          continue;
-        }
-        if (b.kind == BK_ROT && b.pidx >= 0 && ngrad_raw(raw) >= kMaxGradPerPass) {
-          ++it;
-          continue;
-        }
-        for (int bit : need) hsel.insert(bit);
-        if (b.nmask && (b.nmask & P.support())) {
-          // every pending term comes from a diagonal gate whose predecessors
-          // are all placed, so applying all of them here is exact and leaves
-          // fewer, fuller phase ops than flushing only the gate's bits
-          PhasePoly Q = extract_terms(P, n, ~0ull, false);
-          if (!Q.empty) {
-            RawOp ro;
-            ro.kind = OP_PHASE;
-            ro.poly = std::move(Q);
-            raw.push_back(std::move(ro));
-          }
-        }
-        const int kind = b.kind == BK_ROT ? OP_ROT : (b.k == 1 ? OP_DENSE1 : b.k == 2 ? OP_DENSE2 : OP_DENSEK);
-        bool merged = false;
-        if (fuse1 && kind == OP_DENSE1 && !raw.empty()) {
-          RawOp& last = raw.back();
-          if (last.kind == OP_DENSE1 && last.g.tb[0] == b.tb[0] && last.g.cmask == b.cmask) {
-            last.g.mat = matmul(b.mat, last.g.mat, 2);
-            merged = true;
-          }
-        }
-        if (!merged) {
+      if (mg >= 0) {
+        PhasePoly Q = extract_terms(P, n, bg[mg].nmask, false);
+        if (!Q.empty) {
           RawOp ro;
-          ro.kind = kind;
-          ro.g = b;
+          ro.kind = OP_PHASE;
+          ro.poly = std::move(Q);
           raw.push_back(std::move(ro));
         }
-        finish(g, it);
-        progress = true;
-        ++placed;
       }
-    }
-    int mg = -1;  // a ready matrix-core block goes next, after this pass
-    for (int g : ready)
-      if (bg[g].mfma) {
-        mg = g;
-        break;
+      if (scheduled == G && !P.empty) {
+        PhasePoly Q = extract_terms(P, n, ~0ull, true);
+        if (!Q.empty) {
+          RawOp ro;
+          ro.kind = OP_PHASE;
+          ro.poly = std::move(Q);
+          raw.push_back(std::move(ro));
+        }
       }
-    if (mg >= 0) {
-      PhasePoly Q = extract_terms(P, n, bg[mg].nmask, false);
-      if (!Q.empty) {
+      if (scheduled == G && C.tail_phase) {
         RawOp ro;
         ro.kind = OP_PHASE;
-        ro.poly = std::move(Q);
+        ro.poly = *C.tail_phase;
+        ro.scale_idx = 0;
         raw.push_back(std::move(ro));
       }
+      if (placed == 0 && raw.empty() && mg < 0) throw std::runtime_error("planner: no gate fits a tile");
+      close_pass(plan, C, m, L, hsel, raw);
+      if (mg >= 0) {
+        add_mfma_pass(plan, n, bg[mg]);
+        auto it = ready.find(mg);
+        finish(mg, it);
+      }
     }
-    if (scheduled == G && !P.empty) {
+    if (!P.empty) {  // only reachable for an all-diagonal remainder after the loop
       PhasePoly Q = extract_terms(P, n, ~0ull, true);
       if (!Q.empty) {
         RawOp ro;
         ro.kind = OP_PHASE;
         ro.poly = std::move(Q);
         raw.push_back(std::move(ro));
+        close_pass(plan, C, m, L, hsel, raw);
       }
     }
-    if (scheduled == G && C.tail_phase) {
-      RawOp ro;
-      ro.kind = OP_PHASE;
-      ro.poly = *C.tail_phase;
-      ro.scale_idx = 0;
-      raw.push_back(std::move(ro));
-    }
-    if (placed == 0 && raw.empty() && mg < 0) throw std::runtime_error("planner: no gate fits a tile");
-    close_pass(plan, C, m, L, hsel, raw);
-    if (mg >= 0) {
-      add_mfma_pass(plan, n, bg[mg]);
-      auto it = ready.find(mg);
-      finish(mg, it);
-    }
-  }
-  if (!P.empty) {  // only reachable for an all-diagonal remainder after the loop
-    PhasePoly Q = extract_terms(P, n, ~0ull, true);
-    if (!Q.empty) {
-      RawOp ro;
-      ro.kind = OP_PHASE;
-      ro.poly = std::move(Q);
-      raw.push_back(std::move(ro));
-      close_pass(plan, C, m, L, hsel, raw);
-    }
-  }
 
-  // 4. restore the qubit order: sigma[phys[q]] = n-1-q, as two involutions
-  std::vector<int> sigma(n);
-  bool ident = true;
-  for (int q = 0; q < n; ++q) {
-    sigma[phys[q]] = n - 1 - q;
-    ident &= phys[q] == n - 1 - q;
-  }
-  if (!ident) {
-    std::vector<int> t1(n), t2(n);
-    for (int a = 0; a < n; ++a) t1[a] = t2[a] = a;
-    std::vector<bool> seen(n, false);
-    for (int a0 = 0; a0 < n; ++a0) {
-      if (seen[a0]) continue;
-      std::vector<int> cyc;
-      for (int a = a0; !seen[a]; a = sigma[a]) {
-        seen[a] = true;
-        cyc.push_back(a);
-      }
-      const int len = (int)cyc.size();
-      for (int i = 0; i < len; ++i) {
-        t1[cyc[i]] = cyc[((-i) % len + len) % len];
-        t2[cyc[i]] = cyc[((1 - i) % len + len) % len];
-      }
+    // 4. restore the qubit order: sigma[phys[q]] = n-1-q, as two involutions
+    std::vector<int> sigma(n);
+    bool ident = true;
+    for (int q = 0; q < n; ++q) {
+      sigma[phys[q]] = n - 1 - q;
+      ident &= phys[q] == n - 1 - q;
     }
-    int Lp = std::min(L, n);
-    add_perm_pass(plan, n, Lp, dbl, t1);
-    add_perm_pass(plan, n, Lp, dbl, t2);
+    if (!ident) {
+      std::vector<int> t1(n), t2(n);
+      for (int a = 0; a < n; ++a) t1[a] = t2[a] = a;
+      std::vector<bool> seen(n, false);
+      for (int a0 = 0; a0 < n; ++a0) {
+        if (seen[a0]) continue;
+        std::vector<int> cyc;
+        for (int a = a0; !seen[a]; a = sigma[a]) {
+          seen[a] = true;
+          cyc.push_back(a);
+        }
+        const int len = (int)cyc.size();
+        for (int i = 0; i < len; ++i) {
+          t1[cyc[i]] = cyc[((-i) % len + len) % len];
+          t2[cyc[i]] = cyc[((1 - i) % len + len) % len];
+        }
+      }
+      int Lp = std::min(L, n);
+      add_perm_pass(plan, n, Lp, dbl, t1);
+      add_perm_pass(plan, n, Lp, dbl, t2);
+    }
+    return plan;
+  };
+
+  // both schedules; the lookahead one is kept only when it is shorter
+  Plan plan = schedule(false);
+  if (Hmax > 0 && plan.passes.size() > 1) {
+    Plan alt = schedule(true);
+    if (alt.passes.size() < plan.passes.size()) return alt;
   }
   return plan;
 }

@@ -134,6 +134,23 @@ def test_diagonal_only_circuit_is_one_pass(api):
     assert c.info()[1] == 1
 
 
+def test_lookahead_bit_choice_shortens_layered_plans(api):
+    # RY layers with a CZ ring, and RY/RZ layers with a CNOT chain: taking the
+    # high bits that the first gates in index order ask for gives 19 and 23
+    # passes; picking bits along the dependency light cone gives 14 and 11
+    n = 30
+    _, spec, _, _ = qsynth.gradient_20q(seed=0, n=n, layers=10)
+    assert api.Circuit.from_spec(n, spec).info()[1] <= 14
+    chain, k = [], 0
+    for _ in range(5):
+        for q in range(n):
+            for r in ("RY", "RZ"):
+                chain.append(qsynth.gate(r, (q,), theta=0.3, pidx=k))
+                k += 1
+        chain += [qsynth.gate("X", (q + 1,), (q,)) for q in range(n - 1)]
+    assert api.Circuit.from_spec(n, chain).info()[1] <= 11
+
+
 def test_tile_options_change_the_plan(api):
     n = 26
     spec = qsynth.random_layers(n, 4, 3)
