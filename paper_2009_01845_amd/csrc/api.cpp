@@ -1395,6 +1395,7 @@ struct TuneChoice {
   int tile_bits, fuse_k, use_mfma, low_bits;
 };
 
+extern "C++" {  // a C++ helper: std::string result
 std::string tune_key(const qs_circuit* c, const qs_state* s) {
   int dev = 0;
   hipck(hipGetDevice(&dev), "hipGetDevice");
@@ -1408,6 +1409,7 @@ std::string tune_key(const qs_circuit* c, const qs_state* s) {
                 s->dbl() ? "c128" : "c64", arch.c_str(), (unsigned long long)circuit_hash(c->hc));
   return buf;
 }
+}  // extern "C++"
 
 bool cache_lookup(const char* path, const std::string& key, TuneChoice* out) {
   if (!path) return false;

@@ -103,6 +103,40 @@ def test_variational_10q_depth20(api, dt):
 
 
 @pytest.mark.parametrize("dt", DTS)
+def test_rotation_angles_across_periods(api, dt):
+    # X and Y rotations run as three shears of the angle reduced to
+    # [-pi/2, pi/2] times a sign: angles on and between the reduction
+    # boundaries, negative and beyond 4 pi, with an odd and an even count of
+    # sign flips per pass; forward state and adjoint gradient against the oracle
+    n = 14
+    banner("rotation angles", dt)
+    k = np.arange(-8, 9)
+    angles = np.concatenate([k * np.pi / 2, k * np.pi + 0.3, [1e-9, -1e-9, 13.7, -21.2]])
+    spec, params = [], []
+    for layer in range(3):
+        for q in range(n):
+            spec.append(qsynth.gate("RY" if (q + layer) % 2 else "RX", (q,), pidx=len(params)))
+            params.append(angles[(layer * n + q) % len(angles)])
+        spec += [qsynth.gate("Z", (q + 1,), (q,)) for q in range(n - 1)]
+    params = np.array(params)
+    c = api.Circuit.from_spec(n, spec)
+    psi0 = qsynth.random_state(n, 31)
+    st = gpu_state(api, n, dt, psi0)
+    c.run(st, params)
+    ref = ocirc.run(n, spec, oracle_input(psi0, dt), params)
+    assert maxabs(st.download(), ref) < TOL[dt]
+    terms = qsynth.zz_ring_plus_x(n)
+    E_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+    psi, lam = api.State(n, dt), api.State(n, dt)
+    c.run(psi, params)
+    H = api.Observable.pauli_sum(n, terms)
+    E, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+    tol = 1e-10 if dt == "c128" else 1e-4
+    assert abs(E - E_ref) < tol
+    assert np.max(np.abs(g - g_ref)) < tol
+
+
+@pytest.mark.parametrize("dt", DTS)
 def test_qft_random_state_vs_fft(api, dt):
     n = 18
     banner("qft fft", dt, n)
