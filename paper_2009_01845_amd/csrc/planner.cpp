@@ -759,9 +759,8 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
           op.gslot = plan.ngrad_slots++;
           op.aux = ngrad++;
         }
-        // forward and inverse 2x2, then their three-shear parameters, written per run
-        op.mat = (int)plan.matpool.size();
-        plan.matpool.insert(plan.matpool.end(), 12, cd(0, 0));
+        op.mat = (int)plan.matpool.size();  // forward and inverse 2x2, written per run
+        plan.matpool.insert(plan.matpool.end(), 8, cd(0, 0));
       } else {
         const int dim = 1 << bg.k;
         op.mat = (int)plan.matpool.size();

@@ -104,10 +104,9 @@ def test_variational_10q_depth20(api, dt):
 
 @pytest.mark.parametrize("dt", DTS)
 def test_rotation_angles_across_periods(api, dt):
-    # X and Y rotations run as three shears of the angle reduced to
-    # [-pi/2, pi/2] times a sign: angles on and between the reduction
-    # boundaries, negative and beyond 4 pi, with an odd and an even count of
-    # sign flips per pass; forward state and adjoint gradient against the oracle
+    # X and Y rotation angles on multiples of pi/2 and between them, tiny,
+    # negative and beyond 4 pi; forward state and adjoint gradient against
+    # the oracle
     n = 14
     banner("rotation angles", dt)
     k = np.arange(-8, 9)
