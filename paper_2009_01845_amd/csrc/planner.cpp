@@ -723,9 +723,6 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
   for (int b = 0; b < n; ++b) local[b] = -1;
   for (int b = 0; b < L; ++b) local[b] = b;
   for (int j = 0; j < g.H; ++j) local[g.hbits[j]] = L + j;
-  int pos[kMaxTileBits];
-  for (int b = 0; b < L; ++b) pos[b] = b;
-  for (int j = 0; j < g.H; ++j) pos[L + j] = g.hbits[j];
 
   int ngrad = 0;
   for (RawOp& r : raw) {
