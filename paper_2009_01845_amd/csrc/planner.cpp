@@ -12,7 +12,7 @@
 //     passes: the tile bit set T = {0..L-1} U (up to m-L high bits); a gate
 //     joins the open pass when its targets fit in T.  The high bits are those
 //     the first gates in index order ask for, or are picked ahead by how many
-//     gates they unlock; the plan with fewer passes is kept.
+//     gates they unlock (two ways); the plan with the fewest passes is kept.
 #include "planner.h"
 
 #include <algorithm>
@@ -1008,12 +1008,14 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
     }
   }
 
-  // 3. greedy list scheduling into tiled passes.  With lookahead, each pass
-  //    first picks its high bits: starting from the low bits, it repeatedly
-  //    adds the new bits of the blocked gate that unlock the most gates per
-  //    added bit (the gates reachable in dependency order inside the tile);
-  //    then gates are placed in index order as without lookahead.
-  auto schedule = [&](bool lookahead) -> Plan {
+  // 3. greedy list scheduling into tiled passes.  With lookahead (mode 1),
+  //    each pass first picks its high bits: starting from the low bits, it
+  //    repeatedly adds the new bits of the blocked gate that unlock the most
+  //    gates per added bit (the gates reachable in dependency order inside the
+  //    tile); mode 2 also tries every first choice, each completed that way,
+  //    and keeps the set that unlocks the most gates.  Gates are then placed
+  //    in index order as without lookahead (mode 0).
+  auto schedule = [&](int mode) -> Plan {
     Plan plan = proto;
     std::vector<int> indeg = indeg0;
     std::set<int> ready;
@@ -1065,9 +1067,8 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
       touched.clear();
       return cnt;
     };
-    auto pick_bits = [&]() {
-      uint64_t T = lowmask;
-      int nh = 0;
+    // grow the bit set T (nh high bits) greedily by unlocked gates per added bit
+    auto complete = [&](uint64_t T, int nh) {
       std::vector<int> front;
       std::vector<uint64_t> tried;
       while (nh < Hmax) {
@@ -1093,11 +1094,37 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
         T |= pick;
         nh += __builtin_popcountll(pick);
       }
+      return T;
+    };
+    // mode 1: greedy growth; mode 2: every first choice completed greedily,
+    // the set that unlocks the most gates kept
+    auto pick_bits = [&]() {
+      uint64_t T = complete(lowmask, 0);
+      if (mode == 2) {
+        std::vector<int> front;
+        std::vector<uint64_t> tried;
+        closure(lowmask, &front);
+        std::sort(front.begin(), front.end());
+        int best = closure(T, nullptr);
+        for (int g : front) {
+          uint64_t need = 0;
+          for (int t = 0; t < bg[g].k; ++t) need |= (1ull << bg[g].tb[t]) & ~lowmask;
+          const int c = __builtin_popcountll(need);
+          if (c > Hmax || std::find(tried.begin(), tried.end(), need) != tried.end()) continue;
+          tried.push_back(need);
+          const uint64_t T2 = complete(lowmask | need, c);
+          const int cnt = closure(T2, nullptr);
+          if (cnt > best) {
+            best = cnt;
+            T = T2;
+          }
+        }
+      }
       for (uint64_t h = T & ~lowmask; h; h &= h - 1) hsel.insert(__builtin_ctzll(h));
     };
 
     while (scheduled < G) {
-      if (lookahead && hsel.empty()) pick_bits();
+      if (mode && hsel.empty()) pick_bits();
       bool progress = true;
       int placed = 0;
       while (progress) {
@@ -1262,12 +1289,13 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
     return plan;
   };
 
-  // both schedules; the lookahead one is kept only when it is shorter
-  Plan plan = schedule(false);
-  if (Hmax > 0 && plan.passes.size() > 1) {
-    Plan alt = schedule(true);
-    if (alt.passes.size() < plan.passes.size()) return alt;
-  }
+  // the three schedules; a lookahead one is kept only when it is shorter
+  Plan plan = schedule(0);
+  if (Hmax > 0 && plan.passes.size() > 1)
+    for (int mode = 1; mode <= 2; ++mode) {
+      Plan alt = schedule(mode);
+      if (alt.passes.size() < plan.passes.size()) plan = std::move(alt);
+    }
   return plan;
 }
 
