@@ -149,6 +149,11 @@ def test_lookahead_bit_choice_shortens_layered_plans(api):
                 k += 1
         chain += [qsynth.gate("X", (q + 1,), (q,)) for q in range(n - 1)]
     assert api.Circuit.from_spec(n, chain).info()[1] <= 11
+    # a brickwork of Haar 2-qubit gates, depth 12: 31 passes in index order
+    rng = np.random.default_rng(5)
+    brick = [qsynth.gate("MAT", (q, q + 1), mat=qsynth.haar_unitary(4, rng))
+             for d in range(12) for q in range(d % 2, n - 1, 2)]
+    assert api.Circuit.from_spec(n, brick).info()[1] <= 17
 
 
 def test_tile_options_change_the_plan(api):
