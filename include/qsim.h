@@ -144,6 +144,13 @@ qs_status qs_circuit_info(const qs_circuit* c, int32_t* ngates, int32_t* npasses
 /* Describe pass i: kind (1 tile, 2 phase, 3 permutation, 4 mfma, 5 dense),
  * bits held on chip, ops applied. */
 qs_status qs_circuit_pass_info(const qs_circuit* c, int32_t i, int32_t* kind, int32_t* tile_bits, int32_t* nops);
+/* Which choice of high tile bits produced the current plan (Sec. 2.4.5
+ * fusion taken to whole tiles; the planner builds up to three plans and keeps
+ * the one with the fewest passes): 0 = the bits the next gates in list order
+ * need, 1 = greedy lookahead by gates unlocked per added bit, 2 = one-step
+ * rollout over every first choice.  QS_E_STATE if the circuit is not
+ * compiled. */
+qs_status qs_circuit_schedule(const qs_circuit* c, int32_t* schedule);
 qs_status qs_circuit_destroy(qs_circuit* c);
 
 /* ------------------------------------------------------------- observables

@@ -11,6 +11,12 @@ callback of Sec. 2.4.4).  Three independent routes:
 * parameter shift: dE/dtheta = [E(theta + pi/2) - E(theta - pi/2)] / 2, exact
   for exp(-i theta P/2) with P^2 = I and no controls;
 * central finite differences.
+
+For product states (no entangling gate) a fourth, closed-form route:
+every qubit evolves on its own 2-component vector, so <Z_i Z_j> =
+<Z_i><Z_j> and each single-qubit expectation and its derivative come from a
+2x2 evolution (the derivative by the two-term shift rule, which is exact for
+a single exp(-i theta P / 2) acting on one qubit).
 """
 from __future__ import annotations
 
@@ -70,3 +76,64 @@ def finite_difference(n, spec, params, terms, h=1e-6, psi0=None, which=None) -> 
         em = energy(n, spec, p, terms, psi0)
         grad[i] = (ep - em) / (2 * h)
     return grad
+
+
+def _single_qubit_expectations(layers):
+    """<Z> and <X> of RZ(phi_L) RY(theta_L) ... RZ(phi_1) RY(theta_1) |0>
+    for one qubit; layers = [(theta_l, phi_l), ...] (phi may be None)."""
+    v = np.array([1.0, 0.0], dtype=np.complex128)
+    for th, ph in layers:
+        v = gates.matrix("RY", th) @ v
+        if ph is not None:
+            v = gates.matrix("RZ", ph) @ v
+    z = float(np.vdot(v, gates.PAULI["Z"] @ v).real)
+    x = float(np.vdot(v, gates.PAULI["X"] @ v).real)
+    return z, x
+
+
+def product_ring_energy(theta, phi=None, hx=0.5):
+    """Energy and gradient of H = sum_i Z_i Z_{(i+1) mod n} + hx sum_i X_i
+    for the product state prod_q [prod_l RZ(phi[l, q]) RY(theta[l, q])] |0>.
+
+    theta, phi: arrays (layers, n) (phi may be None: RY layers only).  The
+    gradient is returned with the same layout as the parameters of
+    ``qsynth.ry_rz_layers`` (per layer: theta of every qubit, then phi of
+    every qubit) or, without phi, of ``qsynth.ry_layers`` (layer-major)."""
+    theta = np.atleast_2d(np.asarray(theta, dtype=np.float64))
+    Lyr, n = theta.shape
+    ph = None if phi is None else np.atleast_2d(np.asarray(phi, dtype=np.float64))
+
+    def layers_of(q, th_over=None, ph_over=None):
+        out = []
+        for l in range(Lyr):
+            t = theta[l, q] if th_over is None or th_over[0] != l else th_over[1]
+            p = None
+            if ph is not None:
+                p = ph[l, q] if ph_over is None or ph_over[0] != l else ph_over[1]
+            out.append((t, p))
+        return out
+
+    zx = [_single_qubit_expectations(layers_of(q)) for q in range(n)]
+    z = np.array([a for a, _ in zx])
+    x = np.array([b for _, b in zx])
+    if n < 3:
+        raise ValueError("the ring needs at least three qubits")
+    ring = [(i, (i + 1) % n) for i in range(n)]
+    E = sum(z[i] * z[j] for i, j in ring) + hx * float(np.sum(x))
+
+    def dE(q, dz, dx):
+        nb = sum(z[j] for i, j in ring if i == q) + sum(z[i] for i, j in ring if j == q)
+        return dz * nb + hx * dx
+
+    per_layer = 2 if ph is not None else 1
+    grad = np.zeros(Lyr * n * per_layer)
+    for l in range(Lyr):
+        for q in range(n):
+            zp, xp = _single_qubit_expectations(layers_of(q, th_over=(l, theta[l, q] + np.pi / 2)))
+            zm, xm = _single_qubit_expectations(layers_of(q, th_over=(l, theta[l, q] - np.pi / 2)))
+            grad[l * n * per_layer + q] = dE(q, 0.5 * (zp - zm), 0.5 * (xp - xm))
+            if ph is not None:
+                zp, xp = _single_qubit_expectations(layers_of(q, ph_over=(l, ph[l, q] + np.pi / 2)))
+                zm, xm = _single_qubit_expectations(layers_of(q, ph_over=(l, ph[l, q] - np.pi / 2)))
+                grad[l * n * 2 + n + q] = dE(q, 0.5 * (zp - zm), 0.5 * (xp - xm))
+    return float(E), grad

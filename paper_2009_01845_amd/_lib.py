@@ -56,6 +56,7 @@ SIGNATURES = {
     "qs_circuit_run": (_st, [_p, _p, _p, _i32]),
     "qs_circuit_info": (_st, [_p, _i32p, _i32p, _i32p]),
     "qs_circuit_pass_info": (_st, [_p, _i32, _i32p, _i32p, _i32p]),
+    "qs_circuit_schedule": (_st, [_p, _i32p]),
     "qs_circuit_destroy": (_st, [_p]),
     "qs_pauli_sum_create": (_st, [_i32, _i32, _f64p, C.POINTER(C.c_char_p), _pp]),
     "qs_ising_create": (_st, [_i32, _f64p, _f64p, _pp]),

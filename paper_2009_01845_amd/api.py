@@ -169,6 +169,12 @@ def circuit_pass_info(c, i: int):
     return k.value, m.value, o.value
 
 
+def circuit_schedule(c) -> int:
+    v = C.c_int32()
+    check(lib().qs_circuit_schedule(c, C.byref(v)))
+    return v.value
+
+
 def circuit_destroy(c):
     check(lib().qs_circuit_destroy(c))
 
@@ -373,6 +379,9 @@ class Circuit:
 
     def passes(self):
         return [circuit_pass_info(self.h, i) for i in range(self.info()[1])]
+
+    def schedule(self) -> int:
+        return circuit_schedule(self.h)
 
     @property
     def nparams(self):

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .api import Circuit, Observable, State, adjoint
+from .api import Circuit, Observable, State, adjoint, state_copy
 
 
 def _torch():
@@ -33,8 +33,13 @@ def _make_fn():
 
         @staticmethod
         def backward(ctx, g):
+            # the reverse sweep walks its state back to the circuit input, so
+            # it runs on a copy: the saved output stays valid for a repeated
+            # backward (retain_graph, autograd.grad twice, gradcheck)
+            psi = State(ctx.circuit.n, ctx.dtype)
+            state_copy(psi.h, ctx.st.h)
             lam = State(ctx.circuit.n, ctx.dtype)
-            _, grad = adjoint(ctx.circuit.h, ctx.p, ctx.obs.h, ctx.st.h, lam.h, ctx.circuit.nparams)
+            _, grad = adjoint(ctx.circuit.h, ctx.p, ctx.obs.h, psi.h, lam.h, ctx.circuit.nparams)
             out = torch.from_numpy(grad).to(device=ctx.pdevice, dtype=ctx.pdtype) * g.to(ctx.pdevice)
             return out, None, None, None
 

@@ -403,11 +403,22 @@ double download_scalar(const double* dev, hipStream_t s) {
 // sum over the observable's parts (polynomial diagonal, tile sets), each
 // leaving one partial per workgroup in its own kGridMax-long slot; with lam,
 // also lambda = H psi.  Fixed-order sums: the result is deterministic.
-void pauli_pass(qs_state* s, qs_obs* o, void* lam, double* dev_out) {
+// Partial-sum slots of an observable's passes: one for the diagonal
+// polynomial, one per tile set, one per far group.
+int obs_slots(const qs_obs* o) {
+  return (o->poly.empty() ? 0 : 1) + (int)o->sets.size() + (int)o->far.size();
+}
+// doubles of scratch that pauli_pass needs: per slot kGridMax partials, then
+// the slot sums
+size_t pauli_scratch_doubles(const qs_obs* o) {
+  const size_t nslot = (size_t)std::max(obs_slots(o), 1);
+  return (nslot + 1) * kGridMax + nslot + 8;
+}
+
+void pauli_pass(qs_state* s, qs_obs* o, void* lam, double* dev_out, double* part) {
   o->to_device(s->stream);
   const bool poly = !o->poly.empty();
-  const int nslot = (poly ? 1 : 0) + (int)o->sets.size() + (int)o->far.size();
-  double* part = scratch_doubles(s, size_t(nslot + 1) * kGridMax + nslot + 8);
+  const int nslot = obs_slots(o);
   double* slots = part + size_t(nslot) * kGridMax;
   hipck(launch_zero(part, int64_t(std::max(nslot, 1)) * kGridMax, s->stream), "zero");
   int k = 0;
@@ -447,7 +458,15 @@ void pauli_pass(qs_state* s, qs_obs* o, void* lam, double* dev_out) {
 
 void expectation_dev(qs_state* s, qs_obs* o, double* dev_out) {
   ProfScope pr(5, s->stream);
-  pauli_pass(s, o, nullptr, dev_out);
+  pauli_pass(s, o, nullptr, dev_out, scratch_doubles(s, pauli_scratch_doubles(o)));
+}
+
+// A device double for a synchronous result, placed past the scratch that
+// pauli_pass uses (the state's scratch is sized once for both, so the pass
+// does not reallocate it under the result).
+double* expect_result_slot(qs_state* s, const qs_obs* o) {
+  const size_t need = pauli_scratch_doubles(o);
+  return scratch_doubles(s, need + 8) + need;
 }
 
 // Z_p = 1 - 2 x_p on index bit p, so a diagonal group of terms with at most
@@ -853,6 +872,14 @@ qs_status qs_circuit_pass_info(const qs_circuit* c, int32_t i, int32_t* kind, in
   });
 }
 
+qs_status qs_circuit_schedule(const qs_circuit* c, int32_t* schedule) {
+  return guard([&] {
+    if (!c || !schedule) fail(QS_E_INVALID, "null argument");
+    if (!c->planned) fail(QS_E_STATE, "circuit not compiled");
+    *schedule = c->hc.plan.schedule;
+  });
+}
+
 qs_status qs_circuit_destroy(qs_circuit* c) {
   return guard([&] {
     if (!c) return;
@@ -929,8 +956,7 @@ qs_status qs_expectation(const qs_state* cs, const qs_obs* co, double* out) {
       *out = 0.0;
       return;
     }
-    double* part = scratch_doubles(s, size_t(ng + 1) * kGridMax + ng + 8);
-    double* res = part + size_t(ng + 1) * kGridMax;  // past the slot sums
+    double* res = expect_result_slot(s, o);
     expectation_dev(s, o, res);
     *out = download_scalar(res, s->stream);
   });
@@ -1062,9 +1088,7 @@ qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, i
                s->stream);
     if (energy_out) {
       auto* o = const_cast<qs_obs*>(h1);
-      const int ng = (int)o->flips.size();
-      double* part = scratch_doubles(s, size_t(ng + 1) * kGridMax + ng + 8);
-      double* res = part + size_t(ng + 1) * kGridMax;
+      double* res = expect_result_slot(s, o);
       expectation_dev(s, o, res);
       *energy_out = download_scalar(res, s->stream);
     } else {
@@ -1110,7 +1134,7 @@ qs_status qs_adjoint(qs_circuit* c, const double* params, const qs_obs* H, qs_st
     {
       ProfScope pr(7, st);
       c->eout.ensure(sizeof(double));
-      pauli_pass(psi, o, lam->ptr, c->eout.as<double>());
+      pauli_pass(psi, o, lam->ptr, c->eout.as<double>(), scratch_doubles(psi, pauli_scratch_doubles(o)));
       hipck(hipMemcpyAsync(&E, c->eout.p, sizeof(double), hipMemcpyDeviceToHost, st), "energy");
     }
     const int ns = c->hc.plan.ngrad_slots;

@@ -1122,13 +1122,21 @@ __global__ __launch_bounds__(256) void k_samp_shots(const typename CT<R>::C* __r
     else lo = mid + 1;
   }
   const int64_t b = lo;
-  const double incl = wave_incl_scan(lane_mass<R>(psi, N, b, lane));
+  const double mass = lane_mass<R>(psi, N, b, lane);
+  const double incl = wave_incl_scan(mass);
   const double excl = __shfl_up(incl, 1, 64);
   const double before = P[b] + (lane == 0 ? 0.0 : excl);
   const unsigned long long hit = __ballot(P[b] + incl > target);
   int sel;
-  if (hit) sel = __builtin_ctzll(hit);
-  else sel = 63;  // rounding: the target sits past this block's own total
+  if (hit) {
+    sel = __builtin_ctzll(hit);
+  } else {
+    // rounding: the target sits past this block's own total (its lane sums
+    // are added in another order than the block sum).  Take the last lane
+    // that holds any mass, so the outcome never has probability zero
+    const unsigned long long nz = __ballot(mass > 0.0);
+    sel = nz ? 63 - __builtin_clzll(nz) : 63;
+  }
   if (lane == sel) {
     const int64_t first = b * kSampBlock + (int64_t)lane * kSampPerLane;
     double run = before;

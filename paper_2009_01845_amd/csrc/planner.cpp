@@ -27,6 +27,8 @@ namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kPi = 3.141592653589793238462643383279;
+constexpr int kRolloutMaxGates = 6000;  // longer gate lists skip the rollout schedule
+constexpr int kRolloutMaxFront = 48;    // first choices tried per pass by the rollout
 
 bool is_diag(const std::vector<cd>& m, int dim) {
   for (int r = 0; r < dim; ++r)
@@ -1078,6 +1080,7 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
         std::sort(front.begin(), front.end());
         double best = 0.0;
         uint64_t pick = 0;
+        if ((int)front.size() > kRolloutMaxFront) front.resize(kRolloutMaxFront);  // lowest gate indices first
         for (int g : front) {
           uint64_t need = 0;
           for (int t = 0; t < bg[g].k; ++t) need |= (1ull << bg[g].tb[t]) & ~T;
@@ -1106,6 +1109,7 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
         closure(lowmask, &front);
         std::sort(front.begin(), front.end());
         int best = closure(T, nullptr);
+        if ((int)front.size() > kRolloutMaxFront) front.resize(kRolloutMaxFront);  // lowest gate indices first
         for (int g : front) {
           uint64_t need = 0;
           for (int t = 0; t < bg[g].k; ++t) need |= (1ull << bg[g].tb[t]) & ~lowmask;
@@ -1289,12 +1293,19 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
     return plan;
   };
 
-  // the three schedules; a lookahead one is kept only when it is shorter
+  // the three schedules; a lookahead one is kept only when it is shorter.
+  // The rollout costs about |front|^2 * Hmax closure walks per pass, so it
+  // is skipped for very long gate lists
   Plan plan = schedule(0);
+  plan.schedule = 0;
   if (Hmax > 0 && plan.passes.size() > 1)
     for (int mode = 1; mode <= 2; ++mode) {
+      if (mode == 2 && G > kRolloutMaxGates) break;
       Plan alt = schedule(mode);
-      if (alt.passes.size() < plan.passes.size()) plan = std::move(alt);
+      if (alt.passes.size() < plan.passes.size()) {
+        plan = std::move(alt);
+        plan.schedule = mode;
+      }
     }
   return plan;
 }

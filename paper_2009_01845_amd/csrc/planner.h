@@ -82,6 +82,8 @@ struct Plan {
   int ngrad_slots = 0;           // ops carrying a trainable parameter
   int grid_bits = kGridBits;
   bool force_stage = false;
+  int schedule = 0;              // high-bit choice that produced the plan: 0 index order,
+                                 // 1 greedy lookahead, 2 one-step rollout
 };
 
 // Circuit description kept by the C ABI.

@@ -101,6 +101,25 @@ def ry_rz_cz_layers(n: int, params: np.ndarray):
     return out
 
 
+def ry_layers(n: int, params: np.ndarray):
+    """Layers of RY on every qubit, no entangling gate (a product state).
+    ``params`` has shape (layers, n); parameter index = l*n + q."""
+    params = np.atleast_2d(params)
+    return [gate("RY", (q,), theta=params[l, q], pidx=l * n + q)
+            for l in range(params.shape[0]) for q in range(n)]
+
+
+def ry_rz_layers(n: int, theta: np.ndarray, phi: np.ndarray):
+    """Layers of RY on every qubit then RZ on every qubit, no entangling gate.
+    theta, phi: (layers, n); per layer the n RY parameters come first, then
+    the n RZ parameters: index l*2n + q (RY) and l*2n + n + q (RZ)."""
+    out = []
+    for l in range(theta.shape[0]):
+        out += [gate("RY", (q,), theta=theta[l, q], pidx=2 * l * n + q) for q in range(n)]
+        out += [gate("RZ", (q,), theta=phi[l, q], pidx=2 * l * n + n + q) for q in range(n)]
+    return out
+
+
 def ry_czring_layers(n: int, params: np.ndarray):
     """Layers of RY on every qubit then CZ on the ring (i, (i+1) mod n).
     ``params`` has shape (layers, n); parameter index = l*n + q."""

@@ -53,6 +53,14 @@ def test_version_and_gate_matrices(api):
     for name in ["RX", "RY", "RZ", "U1"]:
         for th in (0.0, 0.7, -2.3):
             assert np.allclose(api.gate_matrix(name, th), og.matrix(name, th), atol=1e-15), name
+    # and directly against matrix exponentials: R_P(t) = exp(-i t P/2);
+    # S and T are RZ(pi/2) and RZ(pi/4) times e^{i pi/4} and e^{i pi/8}
+    import scipy.linalg as sla
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    assert np.allclose(api.gate_matrix("S"), np.exp(0.25j * np.pi) * sla.expm(-0.25j * np.pi * Z), atol=1e-15)
+    assert np.allclose(api.gate_matrix("T"), np.exp(0.125j * np.pi) * sla.expm(-0.125j * np.pi * Z), atol=1e-15)
+    for p in "XYZ":
+        assert np.allclose(api.gate_matrix("R" + p, 0.9), sla.expm(-0.45j * og.PAULI[p]), atol=1e-15), p
     with pytest.raises(api.QsError) as e:
         api.gate_matrix("NOPE")
     assert e.value.code == -1
@@ -193,3 +201,29 @@ def test_three_qubit_blocks_widen_for_matrix_cores(api):
     spec10 = [qsynth.gate("MAT", (3, 8, 9), mat=qsynth.haar_unitary(8, rng))]
     small = api.Circuit.from_spec(10, spec10, use_mfma=1)   # 4 + 7 > 10: no matrix cores
     assert 4 not in [k for k, _, _ in small.passes()]
+
+
+def test_schedule_query_and_rollout_planning_time(api):
+    import time
+    n = 20
+    _, spec, _, _ = qsynth.gradient_20q(seed=0, n=n, layers=12)
+    c = api.Circuit.from_spec(n, spec)
+    assert c.schedule() == 2          # the one-step rollout gives the shortest plan here
+    rng = np.random.default_rng(5)
+    brick = [qsynth.gate("MAT", (q, q + 1), mat=qsynth.haar_unitary(4, rng))
+             for d in range(8) for q in range(d % 2, 15, 2)]
+    assert api.Circuit.from_spec(16, brick, tile_bits=8, low_bits=3).schedule() == 2
+    assert api.Circuit.from_spec(16, qsynth.qft(16)).schedule() in (0, 1, 2)
+    raw = api.circuit_create(4)
+    with pytest.raises(api.QsError) as e:
+        api.circuit_schedule(raw)
+    assert e.value.code == -5
+    api.circuit_destroy(raw)
+    # planning cost stays bounded on long layered circuits (the rollout is
+    # capped in first choices and skipped past a gate count)
+    n = 30
+    _, spec, _, _ = qsynth.gradient_20q(seed=1, n=n, layers=60)
+    t = time.perf_counter()
+    c = api.Circuit.from_spec(n, spec)
+    assert time.perf_counter() - t < 60.0
+    assert c.info()[0] == 3600

@@ -14,7 +14,7 @@ from oracle import observables as oobs
 from oracle import sampling as osamp
 from oracle import statevec as osv
 
-from gpu_util import TOL, banner, gpu_state, maxabs, oracle_input
+from gpu_util import TOL, assert_samples_match, banner, gpu_state, maxabs, oracle_input
 
 pytestmark = pytest.mark.gpu
 DTS = ["c64", "c128"]
@@ -86,6 +86,35 @@ def test_random_circuit_tilings(api, dt, ti):
     c.run(st)
     ref = ocirc.run(n, spec, oracle_input(psi0, dt))
     assert maxabs(st.download(), ref) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_rollout_schedule_plans_vs_oracle(api, dt):
+    # plans whose high tile bits the one-step rollout chose: a 2-qubit
+    # brickwork on 8-bit tiles (one LDS sweep per op) and twelve RY + CZ-ring
+    # layers at 20 qubits on 12-bit register-staged tiles (forward and adjoint)
+    banner("rollout plans", dt)
+    n = 16
+    rng = np.random.default_rng(5)
+    brick = [qsynth.gate("MAT", (q, q + 1), mat=qsynth.haar_unitary(4, rng))
+             for d in range(8) for q in range(d % 2, n - 1, 2)]
+    c = api.Circuit.from_spec(n, brick, tile_bits=8, low_bits=3)
+    assert c.schedule() == 2
+    psi0 = qsynth.random_state(n, 61)
+    st = gpu_state(api, n, dt, psi0)
+    c.run(st)
+    assert maxabs(st.download(), ocirc.run(n, brick, oracle_input(psi0, dt))) < TOL[dt]
+    n, spec, params, terms = qsynth.gradient_20q(seed=0, n=20, layers=12)
+    c = api.Circuit.from_spec(n, spec)
+    assert c.schedule() == 2
+    psi, lam = api.State(n, dt), api.State(n, dt)
+    c.run(psi, params)
+    assert maxabs(psi.download(), ocirc.run(n, spec, None, params)) < TOL[dt]
+    if dt == "c128":
+        H = api.Observable.pauli_sum(n, terms)
+        e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+        e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+        assert abs(e - e_ref) < 1e-10 and np.max(np.abs(g - g_ref)) < 1e-10
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -277,7 +306,7 @@ def test_pauli_tile_sets_expectation_and_adjoint(api, dt):
     for terms in (mixed, only_x):
         H = api.Observable.pauli_sum(n, terms)
         assert abs(H.expectation(st) - oobs.expectation(ref, terms).real) < tol * 10
-    gtol = 1e-10 if dt == "c128" else 1e-3  # complex64: 40 terms of |c| ~ 1
+    gtol = 1e-10 if dt == "c128" else 2e-4
     _, spec, params, _ = qsynth.gradient_20q(seed=3, n=n, layers=2)
     c = api.Circuit.from_spec(n, spec)
     for terms in (mixed, only_x):
@@ -301,12 +330,8 @@ def test_sampling_shared_uniforms(api, dt, shots):
     u = np.random.default_rng(shots).random(shots)
     for qubits in (list(range(n)), [4, 0, 9], [12]):
         got = api.sample(st.h, qubits, shots, uniforms=u)
-        exp = osamp.sample(ref, qubits, u)
-        bad = np.nonzero(got != exp)[0]
-        if bad.size:
-            # a mismatch is only acceptable at a CDF boundary (summation order)
-            idx = osamp.sample_indices(ref, u[bad])
-            assert np.all(osamp.boundary_distance(ref, u[bad], idx) < 1e-6), bad
+        # a mismatch is only acceptable at a CDF boundary (summation order)
+        assert_samples_match(got, ref, qubits, u)
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -321,11 +346,7 @@ def test_sampling_block_and_chunk_edges(api, dt, n):
     u = np.random.default_rng(n).random(2000)
     for qubits in (list(range(n)), [n - 1, 0]):
         got = api.sample(st.h, qubits, len(u), uniforms=u)
-        exp = osamp.sample(ref, qubits, u)
-        bad = np.nonzero(got != exp)[0]
-        if bad.size:
-            idx = osamp.sample_indices(ref, u[bad])
-            assert np.all(osamp.boundary_distance(ref, u[bad], idx) < 1e-6), bad
+        assert_samples_match(got, ref, qubits, u)
 
 
 def test_sampling_philox_seed_mode_matches_oracle_generator(api):
@@ -334,9 +355,38 @@ def test_sampling_philox_seed_mode_matches_oracle_generator(api):
     psi0 = qsynth.random_state(n, 2)
     st = gpu_state(api, n, "c128", psi0)
     got = api.sample(st.h, list(range(n)), 3000, seed=0xDEADBEEF12345)
+    # the oracle's own Philox4x32-10 stream (pinned by the published
+    # known-answer vectors) drives the oracle's inverse-CDF draw
     u = osamp.philox_uniforms(0xDEADBEEF12345, 3000)
-    exp = osamp.sample(psi0, list(range(n)), u)
-    assert np.mean(got == exp) > 0.999
+    assert_samples_match(got, psi0, list(range(n)), u)
+    got = api.sample(st.h, [3, 11, 0], 3000, seed=7)
+    assert_samples_match(got, psi0, [3, 11, 0], osamp.philox_uniforms(7, 3000))
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_sampling_sparse_state_never_draws_zero_probability(api, dt):
+    # mass on a few indices of very different size (several in one block,
+    # whole lanes and blocks empty), uniforms on and next to every CDF edge:
+    # wherever rounding moves a draw, it must still land on a nonzero amplitude
+    n = 14
+    banner("sampling sparse", dt)
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    support = [0, 3, 17, 1000, 1023, 1024, 5000, 9000, 16383]
+    mags = [1.0, 1e-9, 0.5, 1e-12, 0.25, 1e-7, 2.0, 1e-15, 0.75]
+    for x, a in zip(support, mags):
+        psi[x] = a * (1 + 0.5j)
+    psi /= np.linalg.norm(psi)
+    st = gpu_state(api, n, dt, psi)
+    ref = oracle_input(psi, dt)
+    p = np.abs(ref) ** 2
+    cdf = np.cumsum(p) / np.sum(p)
+    edges = cdf[np.array(support)]
+    u = np.concatenate([edges, np.nextafter(edges, 0), np.nextafter(np.nextafter(edges, 0), 0),
+                        np.random.default_rng(3).random(20000)])
+    u = u[(u >= 0) & (u < 1)]
+    got = api.sample(st.h, list(range(n)), len(u), uniforms=u)
+    assert np.all(p[got] > 0), np.unique(got[p[got] == 0])
+    assert_samples_match(got, ref, list(range(n)), u)
 
 
 def test_sampling_ghz_and_uniform(api):
@@ -458,36 +508,6 @@ def test_adjoint_variational_12q_vs_parameter_shift(api):
         assert np.max(np.abs(g - g_ps)) < tol, dt
 
 
-@pytest.mark.parametrize("n,dt,tol", [(24, "c128", 1e-9), (30, "c64", 2e-3)])
-def test_adjoint_full_size_vs_parameter_shift(api, n, dt, tol):
-    # beyond 23 qubits every workgroup of a pass walks several tiles: the
-    # two-state pass prefetches the next tile, gradient partials are summed
-    # over tiles and the phase tables take tile-index bits.  RY gates obey
-    # the parameter-shift rule exactly, dE/dt = (E(t + pi/2) - E(t - pi/2)) / 2,
-    # checked on sampled angles against the library's own energies
-    _, spec, params, terms = qsynth.gradient_20q(seed=4, n=n, layers=3)
-    banner("adjoint full size", n, dt)
-    c = api.Circuit.from_spec(n, spec)
-    H = api.Observable.pauli_sum(n, terms)
-    psi = api.State(n, dt)
-    lam = api.State(n, dt)
-    c.run(psi, params)
-    e_fwd = H.expectation(psi)
-    e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
-    del lam
-    assert abs(e - e_fwd) < tol * max(1.0, abs(e_fwd))
-    rng = np.random.default_rng(n)
-    for k in rng.choice(c.nparams, 4, replace=False):
-        ep = []
-        for sgn in (1.0, -1.0):
-            p = params.copy()
-            p[k] += sgn * np.pi / 2
-            psi.set_basis(0)
-            c.run(psi, p)
-            ep.append(H.expectation(psi))
-        assert abs(g[k] - (ep[0] - ep[1]) / 2) < tol * max(1.0, abs(g[k])), (k, g[k], ep)
-
-
 def test_autograd_energy(api):
     import torch
     from paper_2009_01845_amd.autograd import energy
@@ -501,6 +521,13 @@ def test_autograd_energy(api):
     E_ref, g_ref = ograd.adjoint(n, spec, params, terms)
     assert abs(E.item() - E_ref) < 1e-12
     assert np.max(np.abs(p.grad.numpy() - g_ref)) < 1e-10
+    # a second backward through the same graph gives the same gradient
+    p2 = torch.tensor(params, requires_grad=True)
+    E2 = energy(p2, c, H, "c128")
+    g1, = torch.autograd.grad(E2, p2, retain_graph=True)
+    g2, = torch.autograd.grad(E2, p2)
+    assert np.max(np.abs(g1.numpy() - g_ref)) < 1e-10
+    assert np.max(np.abs(g2.numpy() - g_ref)) < 1e-10
 
 
 # ---------------------------------------------------------------- determinism

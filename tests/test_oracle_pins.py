@@ -319,3 +319,62 @@ def test_adjoint_handles_controlled_rotations():
     _, g_adj = gradients.adjoint(n, spec, params, terms)
     g_fd = gradients.finite_difference(n, spec, params, terms, h=1e-6)
     assert np.max(np.abs(g_adj - g_fd)) < 1e-7
+
+
+# ------------------------------------------------------- gate signs (S, T)
+def test_s_and_t_signs_from_rz_exponentials():
+    # S and T are Z rotations by pi/2 and pi/4 up to a global phase:
+    # S = e^{i pi/4} exp(-i (pi/2) Z/2), T = e^{i pi/8} exp(-i (pi/4) Z/2);
+    # the conjugate matrices (which also satisfy T T = S, S S = Z) fail this
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    S_ref = np.exp(0.25j * np.pi) * sla.expm(-0.5j * (np.pi / 2) * Z)
+    T_ref = np.exp(0.125j * np.pi) * sla.expm(-0.5j * (np.pi / 4) * Z)
+    assert np.allclose(gates.matrix("S"), S_ref, atol=1e-15)
+    assert np.allclose(gates.matrix("T"), T_ref, atol=1e-15)
+    assert not np.allclose(gates.matrix("S").conj(), S_ref)
+
+
+# ----------------------------------------------- sampling boundary distances
+def test_boundary_distance_on_a_dyadic_cdf():
+    # four amplitudes 1/2: probabilities 1/4 each, CDF 1/4, 1/2, 3/4, 1 (exact
+    # in binary).  A target on an edge has distance 0, one inside an interval
+    # the smaller gap to its edges
+    psi = np.full(4, 0.5, dtype=complex)
+    u = np.array([0.5, 0.6, 0.1, 0.25, 0.875, 0.0])
+    idx = sampling.sample_indices(psi, u)
+    assert list(idx) == [2, 2, 0, 1, 3, 0]
+    d = sampling.boundary_distance(psi, u, idx)
+    assert np.allclose(d, [0.0, 0.1, 0.1, 0.0, 0.125, 0.0], atol=1e-15)
+    # an index that is not the sampled one: distance to that interval's edges
+    d2 = sampling.boundary_distance(psi, np.array([0.6]), np.array([0]))
+    assert np.isclose(d2[0], 0.35)
+
+
+# ------------------------------------------- product-state energy closed form
+@pytest.mark.parametrize("n", [3, 6])
+def test_ry_layer_ring_energy_closed_form(n):
+    # RY(theta_q)|0> has <Z> = cos theta, <X> = sin theta, so for
+    # H = sum Z_i Z_{i+1 mod n} + 0.5 sum X_i the energy of one RY layer is
+    # E = sum cos t_i cos t_{i+1} + 0.5 sum sin t_i and
+    # dE/dt_k = -sin t_k (cos t_{k-1} + cos t_{k+1}) + 0.5 cos t_k
+    th = np.random.default_rng(n).uniform(0, 2 * np.pi, n)
+    c, s = np.cos(th), np.sin(th)
+    E_formula = float(np.sum(c * np.roll(c, -1)) + 0.5 * np.sum(s))
+    g_formula = -s * (np.roll(c, 1) + np.roll(c, -1)) + 0.5 * c
+    E_cf, g_cf = gradients.product_ring_energy(th[None, :])
+    assert abs(E_cf - E_formula) < 1e-13 and np.max(np.abs(g_cf - g_formula)) < 1e-13
+    spec = qsynth.ry_layers(n, th)
+    E_adj, g_adj = gradients.adjoint(n, spec, th, qsynth.zz_ring_plus_x(n))
+    assert abs(E_adj - E_formula) < 1e-13 and np.max(np.abs(g_adj - g_formula)) < 1e-13
+
+
+def test_product_state_energy_multi_layer_matches_adjoint():
+    n, L = 5, 3
+    rng = np.random.default_rng(11)
+    th, ph = rng.uniform(0, 2 * np.pi, (L, n)), rng.uniform(0, 2 * np.pi, (L, n))
+    spec = qsynth.ry_rz_layers(n, th, ph)
+    params = np.concatenate([np.concatenate([th[l], ph[l]]) for l in range(L)])
+    E_cf, g_cf = gradients.product_ring_energy(th, ph, hx=0.5)
+    E_adj, g_adj = gradients.adjoint(n, spec, params, qsynth.zz_ring_plus_x(n))
+    assert abs(E_cf - E_adj) < 1e-13
+    assert np.max(np.abs(g_cf - g_adj)) < 1e-13
