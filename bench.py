@@ -64,31 +64,70 @@ def load_traffic():
     return float(val.group(1))
 
 
-def cpu_baseline(n: int, budget_s: float = 12.0):
-    """The CPU oracle on a bounded sample of the same workload: QFT-n gates in
-    order on a basis state (numpy, complex128) until the time budget is used."""
+def _host_desc() -> str:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        mem = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES") / 2 ** 30
+    except (ValueError, OSError):
+        mem = float("nan")
+    return f"{model or 'unknown CPU'}, {os.cpu_count()} logical CPUs, {mem:.0f} GiB RAM"
+
+
+def cpu_baseline(n: int, gates: int = 4, reps: int = 3):
+    """The CPU oracle on a bounded sample of the same workload: the first
+    `gates` QFT-n gates in order on a basis state (numpy complex128, a 2^n
+    state), timed `reps` times with the host's BLAS pool and once pinned to
+    core 0 with one BLAS thread; gates/s from the median of the first."""
+    import statistics
+
     import qsynth
     from oracle import gates as og, statevec as sv
-    spec = qsynth.qft(n)
-    psi = sv.basis(n, 12345)
-    done = 0
-    t = time.perf_counter()
-    for g in spec:
-        psi = sv.apply(psi, og.gate_matrix(g), g.targets, g.controls)
-        done += 1
-        if time.perf_counter() - t > budget_s:
-            break
-    dt = time.perf_counter() - t
+    spec = qsynth.qft(n)[:gates]
+    mats = [og.gate_matrix(g) for g in spec]
+
+    def run_once():
+        psi = sv.basis(n, 12345)
+        t = time.perf_counter()
+        for g, U in zip(spec, mats):
+            psi = sv.apply(psi, U, g.targets, g.controls)
+        dt = time.perf_counter() - t
+        del psi
+        return dt
+
     try:
         import threadpoolctl
         thr = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
     except Exception:  # pragma: no cover
-        thr = 1
-    del psi
-    return {"value": done / dt, "unit": "gates/s", "cores": int(thr), "kind": "oracle",
-            "sample": f"first {done} of the {len(spec)} QFT-{n} gates on a basis state, numpy complex128, "
-                      f"{dt:.1f} s (elementwise numpy work runs on one thread; BLAS pool {thr}); "
-                      f"host has {os.cpu_count()} logical CPUs"}
+        threadpoolctl, thr = None, 1
+    times = [run_once() for _ in range(reps)]
+    med = statistics.median(times)
+    pinned = None
+    try:  # one core, one BLAS thread (the paper times single-thread runs with taskset)
+        aff = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(aff)})
+        if threadpoolctl:
+            with threadpoolctl.threadpool_limits(1):
+                pinned = run_once()
+        else:
+            pinned = run_once()
+        os.sched_setaffinity(0, aff)
+    except (AttributeError, OSError):
+        pass
+    return {"value": len(spec) / med, "unit": "gates/s", "cores": int(thr), "kind": "oracle",
+            "sample": f"first {len(spec)} of the {len(qsynth.qft(n))} QFT-{n} gates on a {n}-qubit basis state, "
+                      f"numpy complex128, median of {reps} runs {med:.1f} s (runs {', '.join(f'{x:.1f}' for x in times)} s; "
+                      f"BLAS pool {thr}, numpy's elementwise work on one thread); pinned to one core with one BLAS "
+                      f"thread: {('%.1f s, %.3f gates/s' % (pinned, len(spec) / pinned)) if pinned else 'n/a'}; "
+                      f"host: {_host_desc()}; extrapolated per gate (a plain reference, not an optimised CPU "
+                      f"simulator)",
+            "single_core_gates_per_s": (len(spec) / pinned) if pinned else None}
 
 
 def dense_blocks(n: int, seed: int = 11):
@@ -195,6 +234,8 @@ def main():
     ap.add_argument("--trotter-steps", type=int, default=10)
     ap.add_argument("--autotune", action="store_true", help="pick each 30-qubit circuit's plan by timing first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-gates", type=int, default=4,
+                    help="QFT gates in the oracle's timed prefix (10-40 for the extended baseline)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="per-kernel-kind table instead of the step (one line per case)")
     ap.add_argument("--sweep-dtype", default="c64")
@@ -382,7 +423,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(n)
+        out["cpu_baseline"] = cpu_baseline(n, gates=args.cpu_gates)
     print(json.dumps(out), flush=True)
 
 
