@@ -21,5 +21,7 @@ Module map
   sampling    O6   trace-out marginals, inverse-CDF sampling, Philox4x32-10
   adiabatic   O8   second-order Trotter steps and the exact piecewise reference
   gradients   O9   adjoint recurrence, parameter shift, finite differences
+  evolution        Runge-Kutta and exponential integration of the Schroedinger
+                   equation (Sec. 2.6), entanglement entropy (Sec. 2.4.4)
 """
-from . import gates, statevec, circuits, observables, sampling, adiabatic, gradients  # noqa: F401
+from . import gates, statevec, circuits, observables, sampling, adiabatic, gradients, evolution  # noqa: F401

@@ -378,3 +378,96 @@ def test_product_state_energy_multi_layer_matches_adjoint():
     E_adj, g_adj = gradients.adjoint(n, spec, params, qsynth.zz_ring_plus_x(n))
     assert abs(E_cf - E_adj) < 1e-13
     assert np.max(np.abs(g_cf - g_adj)) < 1e-13
+
+
+# ------------------------------------------------------ ODE evolution, entropy
+def _tfim_terms(n):
+    h0 = [(-1.0, qsynth.pauli_string(n, {q: "X"})) for q in range(n)]
+    J, h = qsynth.ising_couplings(n, 3)
+    return h0, observables.ising_terms(J, h), J, h
+
+
+def test_rk4_step_is_the_fourth_order_taylor_polynomial():
+    # for a constant H the classical Runge-Kutta step is exactly
+    # sum_{j<=4} (-i H dt)^j / j! applied to psi
+    from oracle import evolution as ev
+    n = 4
+    h0, h1, _, _ = _tfim_terms(n)
+    psi = qsynth.random_state(n, 5)
+    H = observables.dense_pauli_sum(n, h1)
+    dt = 0.37
+    got = ev.rk_step(psi, h1, h1, 0.0, dt, 1.0, ev.RK4_A, ev.RK4_B, ev.RK4_C)
+    Z = -1j * dt * H
+    term, exp = psi.copy(), psi.copy()
+    for j in range(1, 5):
+        term = Z @ term / j
+        exp = exp + term
+    assert np.max(np.abs(got - exp)) < 1e-13
+
+
+def test_dormand_prince_weights_satisfy_the_order_conditions():
+    # quadrature conditions sum b_i c_i^(k-1) = 1/k for k = 1..5 and the row
+    # sums of A equal c: a wrong coefficient breaks one of them
+    from oracle import evolution as ev
+    b, c = np.array(ev.DP_B), np.array(ev.DP_C)
+    for k in range(1, 6):
+        assert abs(np.sum(b * c ** (k - 1)) - 1.0 / k) < 1e-14, k
+    for j in range(1, 6):
+        assert abs(sum(ev.DP_A[j]) - c[j]) < 1e-14, j
+    A = np.zeros((6, 6))
+    for j in range(6):
+        A[j, :len(ev.DP_A[j])] = ev.DP_A[j]
+    assert abs(b @ A @ c - 1 / 6) < 1e-14 and abs(b @ A @ c ** 2 - 1 / 12) < 1e-14
+    assert abs(b @ A @ A @ c - 1 / 24) < 1e-14
+
+
+@pytest.mark.parametrize("solver,order", [("rk4", 4), ("rk45", 5)])
+def test_runge_kutta_global_error_order(solver, order):
+    # the final state against the exact piecewise-exponential one on a fine
+    # grid: halving dt divides the error by about 2^order
+    from oracle import evolution as ev
+    n = 4
+    h0, h1, _, _ = _tfim_terms(n)
+    psi0 = np.full(1 << n, 2.0 ** (-n / 2), dtype=complex)
+    T = 1.0
+    ref, _, _ = ev.evolve(n, h0, h1, T, 1 / 2048, "exp", psi0)
+    errs = []
+    for dt in (0.1, 0.05, 0.025):
+        psi, _, _ = ev.evolve(n, h0, h1, T, dt, solver, psi0)
+        errs.append(np.linalg.norm(psi - ref))
+    slope = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
+    assert all(order - 0.5 < s < order + 0.7 for s in slope), (errs, slope)
+
+
+def test_exp_solver_matches_expm_multiply_route():
+    # the dense-exponential steps against the oracle's sparse expm_multiply
+    # route over the same midpoint grid (H0 = -sum X, H1 = Ising)
+    from oracle import evolution as ev
+    n = 6
+    h0, h1, J, h = _tfim_terms(n)
+    E = observables.ising_energies(J, h)
+    psi0 = statevec.plus(n)
+    a, _, _ = ev.evolve(n, h0, h1, 0.5, 0.05, "exp", psi0)
+    b = adiabatic.exact_piecewise(n, E, 0.5, 0.05)
+    assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_entanglement_entropy_closed_forms():
+    from oracle import evolution as ev
+    n = 6
+    # product state: 0; GHZ: log 2 for every cut; Bell pairs (0,3), (1,4):
+    # the cut after qubit 2 crosses two of them
+    prod = circuits.run(n, [qsynth.gate("RY", (q,), theta=0.3 + q) for q in range(n)])
+    ghz = circuits.run(n, qsynth.ghz(n))
+    bell = circuits.run(n, [qsynth.gate("H", (0,)), qsynth.gate("X", (3,), (0,)),
+                            qsynth.gate("H", (1,)), qsynth.gate("X", (4,), (1,))])
+    for a in range(1, n):
+        assert abs(ev.entanglement_entropy(prod, a)) < 1e-12
+        assert abs(ev.entanglement_entropy(ghz, a) - np.log(2)) < 1e-12
+    assert abs(ev.entanglement_entropy(bell, 3) - 2 * np.log(2)) < 1e-12
+    assert abs(ev.entanglement_entropy(bell, 1) - np.log(2)) < 1e-12
+    r = qsynth.random_state(n, 8)
+    for a in range(1, n):  # S(A) = S(B), bounded by min(a, n - a) log 2
+        assert abs(ev.entanglement_entropy(r, a) - ev.entanglement_entropy(
+            r.reshape((2,) * n).transpose(list(range(a, n)) + list(range(a))).reshape(-1), n - a)) < 1e-12
+        assert ev.entanglement_entropy(r, a) <= min(a, n - a) * np.log(2) + 1e-12
