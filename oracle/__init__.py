@@ -23,5 +23,6 @@ Module map
   gradients   O9   adjoint recurrence, parameter shift, finite differences
   evolution        Runge-Kutta and exponential integration of the Schroedinger
                    equation (Sec. 2.6), entanglement entropy (Sec. 2.4.4)
+  density          density matrices, gates and Kraus channels (Sec. 2.4.3)
 """
-from . import gates, statevec, circuits, observables, sampling, adiabatic, gradients, evolution  # noqa: F401
+from . import gates, statevec, circuits, observables, sampling, adiabatic, gradients, evolution, density  # noqa: F401

@@ -32,13 +32,14 @@ def rx_layer(psi: np.ndarray, n: int, angle: float) -> np.ndarray:
     return psi
 
 
-def trotter(n: int, E: np.ndarray, T: float, dt: float, cx=None, psi0=None) -> np.ndarray:
+def trotter(n: int, E: np.ndarray, T: float, dt: float, cx=None, psi0=None, steps=None) -> np.ndarray:
     """Second-order Trotter evolution from the plus state (or psi0).
     E: diagonal energies of H1 over all 2^n indices; cx(s): transverse-field
-    coefficient (default 1 - s, i.e. H0 = -sum X and H1 = diag(E))."""
+    coefficient (default 1 - s, i.e. H0 = -sum X and H1 = diag(E)).  steps:
+    stop after that many steps of the T-schedule (default: all T/dt)."""
     if cx is None:
         cx = lambda s: 1.0 - s  # noqa: E731
-    K = int(round(T / dt))
+    K = int(round(T / dt)) if steps is None else int(steps)
     psi = statevec.plus(n) if psi0 is None else np.asarray(psi0, dtype=np.complex128).copy()
     for k in range(K):
         s = (k + 0.5) * dt / T

@@ -471,3 +471,58 @@ def test_entanglement_entropy_closed_forms():
         assert abs(ev.entanglement_entropy(r, a) - ev.entanglement_entropy(
             r.reshape((2,) * n).transpose(list(range(a, n)) + list(range(a))).reshape(-1), n - a)) < 1e-12
         assert ev.entanglement_entropy(r, a) <= min(a, n - a) * np.log(2) + 1e-12
+
+
+# ------------------------------------------------ density matrices, channels
+@pytest.mark.parametrize("name", ["depolarizing", "amplitude_damping", "phase_damping", "bit_flip", "phase_flip"])
+def test_named_channels_are_trace_preserving(name):
+    from oracle import density
+    for p in (0.0, 0.13, 0.7, 1.0):
+        K = density.kraus(name, p)
+        S = sum(k.conj().T @ k for k in K)
+        assert np.allclose(S, np.eye(2), atol=1e-14), (name, p)
+
+
+def test_named_channels_fixed_points_and_limits():
+    from oracle import density
+    rng = np.random.default_rng(2)
+    psi = qsynth.random_state(1, 4)
+    rho = density.pure(psi)
+    # depolarising with p = 1 gives the maximally mixed state; with p, the
+    # Bloch vector shrinks by 1 - p
+    assert np.allclose(density.apply_channel(rho, density.kraus("depolarizing", 1.0), (0,)), np.eye(2) / 2, atol=1e-14)
+    r = density.apply_channel(rho, density.kraus("depolarizing", 0.3), (0,))
+    assert np.allclose(r, 0.7 * rho + 0.3 * np.eye(2) / 2, atol=1e-14)
+    # amplitude damping with gamma = 1 ends in |0><0|; gamma scales the excited
+    # population and sqrt(1 - gamma) the coherence
+    assert np.allclose(density.apply_channel(rho, density.kraus("amplitude_damping", 1.0), (0,)), np.diag([1, 0]),
+                       atol=1e-14)
+    g = 0.4
+    r = density.apply_channel(rho, density.kraus("amplitude_damping", g), (0,))
+    assert np.isclose(r[1, 1], (1 - g) * rho[1, 1]) and np.isclose(r[0, 1], np.sqrt(1 - g) * rho[0, 1])
+    # phase damping keeps populations and scales coherences by sqrt(1 - lambda)
+    r = density.apply_channel(rho, density.kraus("phase_damping", 0.64), (0,))
+    assert np.allclose(np.diag(r), np.diag(rho)) and np.isclose(r[0, 1], 0.6 * rho[0, 1])
+    # bit flip: (1 - p) rho + p X rho X
+    X = gates.PAULI["X"]
+    r = density.apply_channel(rho, density.kraus("bit_flip", 0.2), (0,))
+    assert np.allclose(r, 0.8 * rho + 0.2 * X @ rho @ X)
+    del rng
+
+
+def test_density_matrix_of_a_unitary_circuit_is_the_pure_state():
+    from oracle import density
+    n = 4
+    spec = qsynth.random_mixed(n, 20, 3, max_k=2, max_ctrl=1)
+    psi = circuits.run(n, spec)
+    rho = density.pure(statevec.zeros(n))
+    for g in spec:
+        rho = density.apply_gate(rho, gates.gate_matrix(g), g.targets, g.controls)
+    assert np.allclose(rho, density.pure(psi), atol=1e-13)
+    terms = qsynth.random_pauli_sum(n, 8, 1)
+    assert abs(density.expectation(rho, terms) - observables.expectation(psi, terms).real) < 1e-12
+    # a channel on two qubits (Kraus operators K x K) keeps the trace
+    K = density.kraus("amplitude_damping", 0.3)
+    K2 = [np.kron(a, b) for a in K for b in K]
+    rho2 = density.apply_channel(rho, K2, (1, 3))
+    assert abs(np.trace(rho2) - 1) < 1e-13
