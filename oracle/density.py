@@ -61,3 +61,20 @@ def kraus(name: str, p: float):
     if name == "phase_flip":
         return [np.sqrt(1 - p) * I2, np.sqrt(p) * Z]
     raise ValueError(name)
+
+
+def run(n: int, spec, rho0=None, params=None) -> np.ndarray:
+    """Apply a ``qsynth`` gate list to rho0 (default |0..0><0..0|); records
+    named ``CH:<channel>`` are channels with parameter theta."""
+    rho = pure(statevec.zeros(n)) if rho0 is None else np.asarray(rho0, dtype=np.complex128).copy()
+    for g in spec:
+        if g.name.startswith("CH:"):
+            rho = apply_channel(rho, kraus(g.name[3:], g.theta), g.targets)
+        else:
+            rho = apply_gate(rho, gates.gate_matrix(g, params), g.targets, g.controls)
+    return rho
+
+
+def as_vector(rho) -> np.ndarray:
+    """rho[r][c] at index r 2^n + c: the 2n-qubit vector the GPU path stores."""
+    return np.asarray(rho, dtype=np.complex128).reshape(-1)

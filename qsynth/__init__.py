@@ -149,6 +149,33 @@ def random_layers(n: int, depth: int, seed: int):
     return out
 
 
+CHANNELS = ("depolarizing", "amplitude_damping", "phase_damping", "bit_flip", "phase_flip")
+
+
+def noisy_layers(n: int, depth: int, seed: int, with_rot: bool = True):
+    """Depth x (Haar 1-qubit gate or trainable RX/RY/RZ on every qubit, CZ on
+    a seeded random matching, then a random named channel with p ~ U[0, 0.3)
+    on two random qubits).  Channel records are named ``CH:<channel>`` with
+    the parameter in theta (density-matrix circuits only)."""
+    rng = np.random.default_rng(seed)
+    out, k = [], 0
+    for _ in range(depth):
+        for q in range(n):
+            if with_rot and rng.random() < 0.5:
+                out.append(gate("R" + "XYZ"[int(rng.integers(3))], (q,), pidx=k))
+                k += 1
+            else:
+                out.append(gate("MAT", (q,), mat=haar_unitary(2, rng)))
+        perm = rng.permutation(n)
+        for i in range(0, n - 1, 2):
+            out.append(gate("Z", (int(perm[i + 1]),), (int(perm[i]),)))
+        for q in rng.choice(n, min(2, n), replace=False):
+            out.append(gate("CH:" + CHANNELS[int(rng.integers(len(CHANNELS)))], (int(q),),
+                            theta=float(rng.uniform(0, 0.3))))
+    params = rng.uniform(0, 2 * pi, k)
+    return out, params
+
+
 def random_mixed(n: int, count: int, seed: int, max_k: int = 2, max_ctrl: int = 2):
     """A random list mixing every gate kind: named gates, rotations, Haar
     matrices on 1..max_k targets, with 0..max_ctrl controls."""

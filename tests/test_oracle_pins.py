@@ -526,3 +526,17 @@ def test_density_matrix_of_a_unitary_circuit_is_the_pure_state():
     K2 = [np.kron(a, b) for a in K for b in K]
     rho2 = density.apply_channel(rho, K2, (1, 3))
     assert abs(np.trace(rho2) - 1) < 1e-13
+
+
+def test_density_run_of_noisy_layers_keeps_trace_and_hermiticity():
+    from oracle import density
+    n = 4
+    spec, params = qsynth.noisy_layers(n, 3, 7)
+    rho = density.run(n, spec, params=params)
+    assert abs(np.trace(rho) - 1) < 1e-13
+    assert np.allclose(rho, rho.conj().T, atol=1e-14)
+    assert np.min(np.linalg.eigvalsh(rho)) > -1e-13
+    # without channels: the pure state of the same gates
+    clean = [g for g in spec if not g.name.startswith("CH:")]
+    assert np.allclose(density.run(n, clean, params=params),
+                       density.pure(circuits.run(n, clean, params=params)), atol=1e-13)
