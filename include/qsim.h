@@ -153,6 +153,46 @@ qs_status qs_circuit_pass_info(const qs_circuit* c, int32_t i, int32_t* kind, in
 qs_status qs_circuit_schedule(const qs_circuit* c, int32_t* schedule);
 qs_status qs_circuit_destroy(qs_circuit* c);
 
+/* -------------------------------------------------------- density matrices
+ * Sec. 2.4.3: circuits that hold noise channels evolve a density matrix
+ * instead of a state vector.  An n-qubit density matrix rho is an ordinary
+ * qs_state of 2n qubits (4^n amplitudes, n <= 17 for QS_C64 and QS_C128 alike
+ * within the 35/34 caps): rho[r][c] sits at flat index r * 2^n + c, so its
+ * row index is held by state qubits 0..n-1 and its column index by state
+ * qubits n..2n-1.  |x><x| is qs_state_set_basis(rho, x * 2^n + x).
+ *
+ * A density-matrix circuit takes qubit numbers of the n-qubit system.  Its
+ * qs_circuit_add_gate(U) applies rho -> U rho U^dagger (U on the row qubits,
+ * conj(U) on the column qubits), qs_circuit_add_rot the same for
+ * exp(-i theta P/2), and qs_circuit_add_channel the map
+ * rho -> sum_i K_i rho K_i^dagger.  qs_circuit_run / compile / info work as
+ * for state vectors on the 2n-qubit rho; qs_adjoint and qs_batch_create
+ * reject density-matrix circuits (QS_E_UNSUPPORTED). */
+qs_status qs_circuit_create_density(int32_t n, qs_circuit** out);
+/* Kraus operators K_0..K_{nkraus-1}: nkraus consecutive 2^k x 2^k complex128
+ * matrices (row-major, interleaved, host), k in {1, 2}, nkraus in [1, 16],
+ * targets[0] the most significant bit of each matrix index.  The map is
+ * applied as given (trace preservation, sum_i K_i^dagger K_i = I, is the
+ * caller's to ensure).  QS_E_STATE on a state-vector circuit. */
+qs_status qs_circuit_add_channel(qs_circuit* c, int32_t nkraus, const double* kraus, int32_t k,
+                                 const int32_t* targets);
+/* Kraus operators of a named one-qubit channel (Nielsen & Chuang, Sec. 8.3),
+ * written as *nkraus_out 2x2 complex128 matrices into out (room for 4):
+ *   "depolarizing"       rho -> (1 - p) rho + p I/2
+ *   "amplitude_damping"  |1> decays to |0> with probability p
+ *   "phase_damping"      off-diagonal terms scaled by sqrt(1 - p)
+ *   "bit_flip", "phase_flip"  X or Z with probability p
+ * p in [0, 1]; *k_out (may be NULL) = 1. */
+qs_status qs_channel_kraus(const char* name, double p, double* out, int32_t* nkraus_out, int32_t* k_out);
+/* rho <- |psi><psi| (rho has 2n qubits of psi's n, same dtype); enqueued on
+ * rho's stream after psi's stream has finished. */
+qs_status qs_density_set_pure(qs_state* rho, const qs_state* psi);
+/* Re Tr(H rho) in float64 for an observable H on the n-qubit system (Pauli
+ * sum or Ising form); synchronises rho's stream. */
+qs_status qs_density_expectation(const qs_state* rho, const qs_obs* H, double* out);
+/* Re Tr(rho) in float64; synchronises rho's stream. */
+qs_status qs_density_trace(const qs_state* rho, double* out);
+
 /* ------------------------------------------------------------- observables
  * Sec. 2.4.4: energy = <psi|H|psi>.  H = sum_t coeffs[t] * P_t with each
  * strings[t] a NUL-terminated length-n word over {I,X,Y,Z}; character j acts
@@ -191,6 +231,59 @@ qs_status qs_sample(const qs_state* s, int32_t m, const int32_t* qubits, int64_t
  * the ground state of H0).  energy_out (may be NULL) receives <H1> at the end. */
 qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, int32_t order,
                            double* energy_out);
+
+/* ------------------------------------------------------------- callbacks
+ * Sec. 2.4.4: quantities computed on intermediate states during an
+ * evolution.  After every `every` time steps (steps every, 2 every, ...,
+ * K = T/dt of them in all) the run records, into entry i of the host arrays:
+ *   energies[i]  = Re <psi|energy|psi> (float64), if energy is not NULL;
+ *   entropies[i] = the entanglement entropy of qubits 0..entropy_qubits-1
+ *                  against the rest (see qs_entanglement_entropy), if
+ *                  entropy_qubits > 0.
+ * Each array needs room for K / every values (integer division). */
+typedef struct qs_callbacks {
+  int32_t every;
+  int32_t entropy_qubits;
+  const qs_obs* energy;
+  double* energies;
+  double* entropies;
+} qs_callbacks;
+
+/* Entanglement entropy -Tr(rho_A ln rho_A) of the first a qubits (qubits
+ * 0..a-1), rho_A = M M^dagger with M = psi viewed as a 2^a x 2^(n-a) matrix
+ * (rho_A is not renormalised; eigenvalues below 1e-15 contribute nothing).
+ * The Gram matrix of the smaller side is formed on the GPU (complex128
+ * matrix-core products) and its eigenvalues on the host, so
+ * min(a, n - a) <= 10.  a in [1, n-1].  Synchronises the state's stream. */
+qs_status qs_entanglement_entropy(const qs_state* s, int32_t a, double* out);
+
+/* Same as qs_adiabatic_run, recording the callbacks (cb may be NULL).  The
+ * run is split at the callback steps: each segment closes its last half
+ * rotation layer, so the recorded states are the Trotter states after those
+ * steps. */
+qs_status qs_adiabatic_run_callbacks(qs_state* s, const qs_obs* h1, double T, double dt, int32_t order,
+                                     const qs_callbacks* cb, double* energy_out);
+
+/* ---------------------------------------------------------- ODE evolution
+ * Sec. 2.6: integrate i dpsi/dt = H(t) psi with H(t) = (1 - t/T) h0 + (t/T) h1
+ * (h0, h1 any observables of the state's n) over K = T/dt steps, in place.
+ *   QS_SOLVER_EXP   each step multiplies psi by exp(-i H(s_k) dt), H at the
+ *                   step midpoint s_k = (k + 1/2) dt / T, built as a dense
+ *                   2^n x 2^n complex128 matrix; the exponential by scaling
+ *                   and squaring of its Taylor series (terms until the
+ *                   remainder bound is below 1e-18), every product on FP64
+ *                   matrix cores.  n <= 12.
+ *   QS_SOLVER_RK4   classical four-stage Runge-Kutta on the continuous
+ *                   schedule, H psi applied term by term from the Pauli sums.
+ *   QS_SOLVER_RK45  Dormand-Prince 5(4) tableau with the fixed step dt,
+ *                   advancing the fifth-order solution.
+ * The Runge-Kutta solvers keep 2 + (4 or 7) state-sized buffers.  cb may be
+ * NULL.  Synchronises the state's stream. */
+#define QS_SOLVER_EXP 1
+#define QS_SOLVER_RK4 2
+#define QS_SOLVER_RK45 3
+qs_status qs_evolve(qs_state* s, const qs_obs* h0, const qs_obs* h1, double T, double dt, int32_t solver,
+                    const qs_callbacks* cb);
 
 /* ---------------------------------------------------------------- gradient
  * Adjoint differentiation (Jones & Gacon 2020; not in the paper): on entry

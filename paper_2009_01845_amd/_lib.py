@@ -20,6 +20,11 @@ class QsError(RuntimeError):
         self.code = code
 
 
+class Callbacks(C.Structure):
+    _fields_ = [("every", C.c_int32), ("entropy_qubits", C.c_int32), ("energy", C.c_void_p),
+                ("energies", C.POINTER(C.c_double)), ("entropies", C.POINTER(C.c_double))]
+
+
 class Tune(C.Structure):
     _fields_ = [("tile_bits", C.c_int32), ("fuse_k", C.c_int32), ("use_mfma", C.c_int32),
                 ("low_bits", C.c_int32), ("reserved", C.c_int32 * 4)]
@@ -58,6 +63,12 @@ SIGNATURES = {
     "qs_circuit_pass_info": (_st, [_p, _i32, _i32p, _i32p, _i32p]),
     "qs_circuit_schedule": (_st, [_p, _i32p]),
     "qs_circuit_destroy": (_st, [_p]),
+    "qs_circuit_create_density": (_st, [_i32, _pp]),
+    "qs_circuit_add_channel": (_st, [_p, _i32, _f64p, _i32, _i32p]),
+    "qs_density_set_pure": (_st, [_p, _p]),
+    "qs_channel_kraus": (_st, [C.c_char_p, C.c_double, _f64p, _i32p, _i32p]),
+    "qs_density_expectation": (_st, [_p, _p, _f64p]),
+    "qs_density_trace": (_st, [_p, _f64p]),
     "qs_pauli_sum_create": (_st, [_i32, _i32, _f64p, C.POINTER(C.c_char_p), _pp]),
     "qs_ising_create": (_st, [_i32, _f64p, _f64p, _pp]),
     "qs_obs_destroy": (_st, [_p]),
@@ -66,6 +77,9 @@ SIGNATURES = {
     "qs_norm2": (_st, [_p, _f64p]),
     "qs_sample": (_st, [_p, _i32, _i32p, _i64, _u64, _f64p, C.POINTER(C.c_int64)]),
     "qs_adiabatic_run": (_st, [_p, _p, C.c_double, C.c_double, _i32, _f64p]),
+    "qs_entanglement_entropy": (_st, [_p, _i32, _f64p]),
+    "qs_adiabatic_run_callbacks": (_st, [_p, _p, C.c_double, C.c_double, _i32, C.POINTER(Callbacks), _f64p]),
+    "qs_evolve": (_st, [_p, _p, _p, C.c_double, C.c_double, _i32, C.POINTER(Callbacks)]),
     "qs_adjoint": (_st, [_p, _f64p, _p, _p, _p, _f64p, _f64p]),
     "qs_batch_create": (_st, [_i32, _pp, _pp, _i32, _p, _pp]),
     "qs_batch_run": (_st, [_p, _f64p, _f64p, _f64p]),

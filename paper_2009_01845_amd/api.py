@@ -12,6 +12,7 @@ from typing import Iterable, Sequence
 
 import numpy as np
 
+from . import _lib as _lib_mod
 from ._lib import QS_C64, QS_C128, QsError, Tune, check, lib  # noqa: F401
 
 _F64P = C.POINTER(C.c_double)
@@ -179,6 +180,43 @@ def circuit_destroy(c):
     check(lib().qs_circuit_destroy(c))
 
 
+def circuit_create_density(n: int):
+    h = C.c_void_p()
+    check(lib().qs_circuit_create_density(n, C.byref(h)))
+    return h
+
+
+def channel_kraus(name: str, p: float) -> list:
+    buf = np.zeros(2 * 4 * 16)
+    nk, k = C.c_int32(), C.c_int32()
+    check(lib().qs_channel_kraus(name.encode(), float(p), buf.ctypes.data_as(_F64P), C.byref(nk), C.byref(k)))
+    d = 1 << k.value
+    z = buf[0::2] + 1j * buf[1::2]
+    return [z[i * d * d:(i + 1) * d * d].reshape(d, d) for i in range(nk.value)]
+
+
+def circuit_add_channel(c, kraus, targets: Sequence[int]):
+    mats = [np.asarray(K, dtype=np.complex128) for K in kraus]
+    keep, mp = _mat_arg(np.concatenate([K.ravel() for K in mats]))
+    check(lib().qs_circuit_add_channel(c, len(mats), mp, len(targets), _i32(targets)))
+
+
+def density_set_pure(rho, psi):
+    check(lib().qs_density_set_pure(rho, psi))
+
+
+def density_expectation(rho, o) -> float:
+    v = C.c_double()
+    check(lib().qs_density_expectation(rho, o, C.byref(v)))
+    return v.value
+
+
+def density_trace(rho) -> float:
+    v = C.c_double()
+    check(lib().qs_density_trace(rho, C.byref(v)))
+    return v.value
+
+
 def pauli_sum_create(n: int, terms: Iterable):
     terms = list(terms)
     co = np.array([float(c) for c, _ in terms])
@@ -233,6 +271,48 @@ def adiabatic_run(h, h1, T: float, dt: float, order: int = 2) -> float:
     e = C.c_double()
     check(lib().qs_adiabatic_run(h, h1, float(T), float(dt), int(order), C.byref(e)))
     return e.value
+
+
+SOLVERS = {"exp": 1, "rk4": 2, "rk45": 3}
+
+
+def _callbacks(K: int, every: int, energy=None, entropy_qubits: int = 0):
+    """A qs_callbacks record and its output arrays (K / every values each)."""
+    if not every:
+        return None, None, None
+    cnt = max(1, K // every)
+    en = np.zeros(cnt)
+    ent = np.zeros(cnt)
+    cb = _lib_mod.Callbacks(int(every), int(entropy_qubits), energy.h if energy is not None else None,
+                            en.ctypes.data_as(_F64P), ent.ctypes.data_as(_F64P))
+    return cb, en, ent
+
+
+def entanglement_entropy(h, a: int) -> float:
+    v = C.c_double()
+    check(lib().qs_entanglement_entropy(h, int(a), C.byref(v)))
+    return v.value
+
+
+def evolve(h, h0, h1, T: float, dt: float, solver: str = "exp", every: int = 0, energy=None,
+           entropy_qubits: int = 0):
+    """Integrate the Schroedinger equation (h0, h1: Observable).  Returns the
+    recorded (energies, entropies) when every > 0, else (None, None)."""
+    K = int(round(T / dt))
+    cb, en, ent = _callbacks(K, every, energy, entropy_qubits)
+    check(lib().qs_evolve(h, h0.h, h1.h, float(T), float(dt), SOLVERS[solver], C.byref(cb) if cb else None))
+    return (en if energy is not None else None, ent if entropy_qubits else None) if cb else (None, None)
+
+
+def adiabatic_run_callbacks(h, h1, T: float, dt: float, every: int, energy=None, entropy_qubits: int = 0,
+                            order: int = 2):
+    """Trotter evolution with callbacks; returns (final <H1>, energies, entropies)."""
+    K = int(round(T / dt))
+    cb, en, ent = _callbacks(K, every, energy, entropy_qubits)
+    e = C.c_double()
+    check(lib().qs_adiabatic_run_callbacks(h, h1.h, float(T), float(dt), int(order), C.byref(cb) if cb else None,
+                                           C.byref(e)))
+    return e.value, (en if energy is not None else None), (ent if entropy_qubits else None)
 
 
 def adjoint(c, params, H, psi, lam, nparams: int):
@@ -395,6 +475,65 @@ class Circuit:
             except Exception:
                 pass
             self.h = None
+
+
+class DensityMatrix:
+    """An n-qubit density matrix held as a 2n-qubit state (rho[r][c] at
+    r * 2^n + c), initialised to |0..0><0..0|."""
+
+    def __init__(self, n: int, dtype="c64", stream=None):
+        self.n = n
+        self.state = State(2 * n, dtype, stream=stream)
+        self.h = self.state.h
+
+    def set_pure(self, psi: State):
+        density_set_pure(self.h, psi.h)
+
+    def set_basis(self, x: int):
+        state_set_basis(self.h, (int(x) << self.n) | int(x))
+
+    def expectation(self, obs: Observable) -> float:
+        return density_expectation(self.h, obs.h)
+
+    def trace(self) -> float:
+        return density_trace(self.h)
+
+    def download(self) -> np.ndarray:
+        return self.state.download().reshape(1 << self.n, 1 << self.n)
+
+    def upload(self, rho: np.ndarray):
+        self.state.upload(np.asarray(rho).reshape(-1))
+
+
+class DensityCircuit(Circuit):
+    """A circuit acting on density matrices (Sec. 2.4.3): gates as
+    U rho U^dagger, channels as sum_i K_i rho K_i^dagger."""
+
+    def __init__(self, n: int):
+        self.n = n
+        self.h = circuit_create_density(n)
+
+    @classmethod
+    def from_spec(cls, n: int, spec, **compile_opts):
+        """``qsynth.G`` records; ``CH:<channel>`` records are named channels
+        with their parameter in theta."""
+        c = cls(n)
+        for g in spec:
+            if g.name.startswith("CH:"):
+                circuit_add_channel(c.h, channel_kraus(g.name[3:], g.theta), g.targets)
+            elif g.pidx >= 0:
+                circuit_add_rot(c.h, g.name[1], g.targets[0], g.pidx, g.controls)
+            else:
+                m = g.mat if g.name == "MAT" else gate_matrix(g.name, g.theta)
+                circuit_add_gate(c.h, m, g.targets, g.controls)
+        c.compile(**compile_opts)
+        return c
+
+    def add_channel(self, kraus, targets):
+        circuit_add_channel(self.h, kraus, targets)
+
+    def run(self, rho: DensityMatrix, params=None):
+        circuit_run(self.h, rho.h, params)
 
 
 # ---------------------------------------------------------------------- batch

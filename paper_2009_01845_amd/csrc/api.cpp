@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -16,6 +17,7 @@
 
 #include "../../include/qsim.h"
 #include "kernels.h"
+#include "linalg.h"
 #include "planner.h"
 
 using namespace qs;
@@ -238,6 +240,7 @@ struct qs_state {
 
 struct qs_circuit {
   HostCircuit hc;
+  int dens = 0;  // density-matrix circuit on dens qubits (hc.n = 2 dens), 0 for state vectors
   bool planned = false;
   bool plan_dbl = false;
   TuneOpts plan_opts;
@@ -750,6 +753,43 @@ qs_status qs_gate_matrix(const char* name, double theta, double* out, int32_t* k
   });
 }
 
+// Kraus operators of the textbook one-qubit channels (Nielsen & Chuang,
+// Sec. 8.3): depolarising rho -> (1 - p) rho + p I/2, amplitude damping with
+// decay probability p, phase damping with parameter p, bit and phase flip
+// with probability p.
+qs_status qs_channel_kraus(const char* name, double p, double* out, int32_t* nkraus_out, int32_t* k_out) {
+  return guard([&] {
+    if (!name || !out || !nkraus_out) fail(QS_E_INVALID, "null argument");
+    if (!(p >= 0.0 && p <= 1.0)) fail(QS_E_INVALID, "channel parameter must be in [0, 1]");
+    const std::string nm(name);
+    std::vector<std::array<cd, 4>> ks;
+    const cd z(0, 0), one(1, 0), im(0, 1);
+    if (nm == "depolarizing") {
+      const double a = std::sqrt(1.0 - 0.75 * p), b = std::sqrt(0.25 * p);
+      ks = {{a * one, z, z, a * one}, {z, b * one, b * one, z}, {z, -b * im, b * im, z}, {b * one, z, z, -b * one}};
+    } else if (nm == "amplitude_damping") {
+      ks = {{one, z, z, std::sqrt(1.0 - p) * one}, {z, std::sqrt(p) * one, z, z}};
+    } else if (nm == "phase_damping") {
+      ks = {{one, z, z, std::sqrt(1.0 - p) * one}, {z, z, z, std::sqrt(p) * one}};
+    } else if (nm == "bit_flip") {
+      const double a = std::sqrt(1.0 - p), b = std::sqrt(p);
+      ks = {{a * one, z, z, a * one}, {z, b * one, b * one, z}};
+    } else if (nm == "phase_flip") {
+      const double a = std::sqrt(1.0 - p), b = std::sqrt(p);
+      ks = {{a * one, z, z, a * one}, {b * one, z, z, -b * one}};
+    } else {
+      fail(QS_E_INVALID, "unknown channel " + nm);
+    }
+    for (size_t t = 0; t < ks.size(); ++t)
+      for (int i = 0; i < 4; ++i) {
+        out[8 * t + 2 * i] = ks[t][i].real();
+        out[8 * t + 2 * i + 1] = ks[t][i].imag();
+      }
+    *nkraus_out = (int32_t)ks.size();
+    if (k_out) *k_out = 1;
+  });
+}
+
 qs_status qs_apply(qs_state* s, const double* mat, int32_t k, const int32_t* targets, int32_t nctrl,
                    const int32_t* controls) {
   return guard([&] {
@@ -775,11 +815,69 @@ qs_status qs_circuit_create(int32_t n, qs_circuit** out) {
   });
 }
 
+qs_status qs_circuit_create_density(int32_t n, qs_circuit** out) {
+  return guard([&] {
+    if (!out) fail(QS_E_INVALID, "null output handle");
+    *out = nullptr;
+    if (n < 1 || 2 * n > QS_MAX_QUBITS_C64) fail(QS_E_INVALID, "n out of range (a density matrix needs 2n <= 35)");
+    auto c = new qs_circuit;
+    c->hc.n = 2 * n;
+    c->dens = n;
+    *out = c;
+  });
+}
+
 qs_status qs_circuit_add_gate(qs_circuit* c, const double* mat, int32_t k, const int32_t* targets, int32_t nctrl,
                               const int32_t* controls) {
   return guard([&] {
     if (!c) fail(QS_E_INVALID, "null circuit");
-    c->hc.gates.push_back(make_gate(c->hc.n, mat, k, targets, nctrl, controls));
+    Gate g = make_gate(c->dens ? c->dens : c->hc.n, mat, k, targets, nctrl, controls);
+    if (c->dens) {
+      // U rho U^dagger: U on the row qubits, conj(U) on the column qubits
+      Gate gc = g;
+      for (int i = 0; i < gc.k; ++i) gc.tq[i] += c->dens;
+      for (int& q : gc.cq) q += c->dens;
+      for (cd& v : gc.mat) v = std::conj(v);
+      c->hc.gates.push_back(std::move(g));
+      c->hc.gates.push_back(std::move(gc));
+    } else {
+      c->hc.gates.push_back(std::move(g));
+    }
+    c->planned = false;
+  });
+}
+
+qs_status qs_circuit_add_channel(qs_circuit* c, int32_t nkraus, const double* kraus, int32_t k,
+                                 const int32_t* targets) {
+  return guard([&] {
+    if (!c) fail(QS_E_INVALID, "null circuit");
+    if (!c->dens) fail(QS_E_STATE, "channels need a density-matrix circuit (qs_circuit_create_density)");
+    if (k < 1 || k > 2) fail(QS_E_INVALID, "a channel acts on 1 or 2 qubits");
+    if (nkraus < 1 || nkraus > 16) fail(QS_E_INVALID, "nkraus must be in [1, 16]");
+    if (!kraus || !targets) fail(QS_E_INVALID, "null Kraus operators or targets");
+    std::string err = validate_gate(c->dens, k, targets, 0, nullptr);
+    if (!err.empty()) fail(QS_E_INVALID, err);
+    const int d = 1 << k, dd = d * d;
+    // superoperator S = sum_i K_i (x) conj(K_i) on (row targets, column targets):
+    // S[(r, c), (r', c')] = sum_i K_i[r][r'] conj(K_i[c][c'])
+    Gate g;
+    g.k = 2 * k;
+    for (int i = 0; i < k; ++i) {
+      g.tq[i] = targets[i];
+      g.tq[k + i] = targets[i] + c->dens;
+    }
+    g.mat.assign(size_t(dd) * dd, cd(0, 0));
+    for (int t = 0; t < nkraus; ++t) {
+      const std::vector<cd> K = read_matrix(kraus + size_t(t) * 2 * dd, k);
+      for (const cd& v : K)
+        if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) fail(QS_E_INVALID, "non-finite Kraus entry");
+      for (int r = 0; r < d; ++r)
+        for (int cc = 0; cc < d; ++cc)
+          for (int r2 = 0; r2 < d; ++r2)
+            for (int c2 = 0; c2 < d; ++c2)
+              g.mat[size_t(r * d + cc) * dd + (r2 * d + c2)] += K[r * d + r2] * std::conj(K[cc * d + c2]);
+    }
+    c->hc.gates.push_back(std::move(g));
     c->planned = false;
   });
 }
@@ -790,7 +888,7 @@ qs_status qs_circuit_add_rot(qs_circuit* c, char pauli, int32_t target, int32_t 
     if (!c) fail(QS_E_INVALID, "null circuit");
     if (pauli != 'X' && pauli != 'Y' && pauli != 'Z') fail(QS_E_INVALID, "pauli must be X, Y or Z");
     if (param_index < 0) fail(QS_E_INVALID, "negative parameter index");
-    std::string err = validate_gate(c->hc.n, 1, &target, nctrl, controls);
+    std::string err = validate_gate(c->dens ? c->dens : c->hc.n, 1, &target, nctrl, controls);
     if (!err.empty()) fail(QS_E_INVALID, err);
     Gate g;
     g.k = 1;
@@ -800,6 +898,14 @@ qs_status qs_circuit_add_rot(qs_circuit* c, char pauli, int32_t target, int32_t 
     g.pauli = pauli;
     g.pidx = param_index;
     c->hc.gates.push_back(g);
+    if (c->dens) {
+      // conj(exp(-i theta P/2)) = exp(-i (-theta) P/2) for X and Z (real P),
+      // exp(-i theta Y/2) for Y (Y* = -Y)
+      g.tq[0] += c->dens;
+      for (int& q : g.cq) q += c->dens;
+      g.rsign = pauli == 'Y' ? 1 : -1;
+      c->hc.gates.push_back(g);
+    }
     c->hc.nparams = std::max(c->hc.nparams, param_index + 1);
     c->planned = false;
   });
@@ -989,6 +1095,51 @@ qs_status qs_norm2(const qs_state* cs, double* out) {
   });
 }
 
+// ------------------------------------------------------- density matrices
+qs_status qs_density_set_pure(qs_state* rho, const qs_state* psi) {
+  return guard([&] {
+    check_state(rho);
+    check_state(psi);
+    if (rho->n != 2 * psi->n || rho->dt != psi->dt)
+      fail(QS_E_STATE, "rho must have 2n qubits of psi's n and the same dtype");
+    ProfScope pr(9, rho->stream);
+    if (psi->stream != rho->stream) hipck(hipStreamSynchronize(psi->stream), "hipStreamSynchronize");
+    hipck(launch_outer(rho->dbl(), rho->ptr, psi->ptr, psi->n, rho->stream), "outer product");
+  });
+}
+
+qs_status qs_density_expectation(const qs_state* crho, const qs_obs* co, double* out) {
+  return guard([&] {
+    check_state(crho);
+    if (!co || !out) fail(QS_E_INVALID, "null argument");
+    if (crho->n % 2 != 0 || co->n * 2 != crho->n) fail(QS_E_STATE, "rho must have twice the observable's qubits");
+    auto* s = const_cast<qs_state*>(crho);
+    auto* o = const_cast<qs_obs*>(co);
+    o->to_device(s->stream);
+    double* part = scratch_doubles(s, kGridMax + 8);
+    ProfScope pr(5, s->stream);
+    hipck(launch_dens_pauli(s->dbl(), s->ptr, o->n, o->dflips.as<uint64_t>(), o->dgoff.as<int32_t>(),
+                            o->dterms.as<PauliTermDev>(), (int)o->flips.size(), part, part + kGridMax, s->stream),
+          "Tr(H rho)");
+    *out = download_scalar(part + kGridMax, s->stream);
+  });
+}
+
+qs_status qs_density_trace(const qs_state* crho, double* out) {
+  return guard([&] {
+    check_state(crho);
+    if (!out) fail(QS_E_INVALID, "null output");
+    if (crho->n % 2 != 0) fail(QS_E_STATE, "a density matrix has an even number of vector qubits");
+    auto* s = const_cast<qs_state*>(crho);
+    double* part = scratch_doubles(s, kGridMax + 8);
+    ProfScope pr(5, s->stream);
+    hipck(launch_dens_pauli(s->dbl(), s->ptr, s->n / 2, nullptr, nullptr, nullptr, 0, part, part + kGridMax,
+                            s->stream),
+          "Tr(rho)");
+    *out = download_scalar(part + kGridMax, s->stream);
+  });
+}
+
 // ---------------------------------------------------------------- sampling
 qs_status qs_sample(const qs_state* cs, int32_t m, const int32_t* qubits, int64_t shots, uint64_t seed,
                     const double* uniforms, int64_t* out) {
@@ -1037,55 +1188,191 @@ qs_status qs_sample(const qs_state* cs, int32_t m, const int32_t* qubits, int64_
 }
 
 // ---------------------------------------------------------------- adiabatic
+}  // extern "C"
+
+namespace {
+
+int64_t step_count(double T, double dt) {
+  if (!(T > 0) || !(dt > 0) || !std::isfinite(T) || !std::isfinite(dt)) fail(QS_E_INVALID, "T and dt must be > 0");
+  const double kf = T / dt;
+  const int64_t K = (int64_t)std::llround(kf);
+  if (K < 1 || std::fabs(kf - (double)K) > 1e-9 * std::max(1.0, kf)) fail(QS_E_INVALID, "T/dt must be an integer");
+  return K;
+}
+
+// Trotter steps k0 .. k1-1 of the schedule s_k = (k + 1/2) dt / T, each with
+// its half rotation layers: the segment opens with the first half layer of
+// step k0 and closes with the second half layer of step k1 - 1.  Blocks of S
+// steps share passes (the last pass of a step carries the next step's
+// rotations on its tile bits): up to 16 steps form one block, longer segments
+// replay blocks of 8, and the last block also carries the closing layer.
+// Plans depend only on the block length, so they are cached in `plans`.
+struct TrotterPlans {
+  std::map<std::pair<int, bool>, std::pair<Plan, std::unique_ptr<DevPlanBuf>>> m;
+};
+
+void trotter_segment(qs_state* s, const PhasePoly& E, double T, double dt, int64_t k0, int64_t k1, TrotterPlans& tp) {
+  const int n = s->n;
+  const bool dbl = s->dbl();
+  const int64_t K = k1 - k0;
+  const int S = (int)(K <= 16 ? K : 8);
+  const int64_t rem = K % S;
+  const int64_t nfull = K / S - (rem ? 0 : 1);  // blocks before the last segment
+  const int L = (int)(rem ? rem : S);           // steps of the last segment
+  auto get = [&](int steps, bool final) -> std::pair<Plan, std::unique_ptr<DevPlanBuf>>& {
+    auto key = std::make_pair(steps, final);
+    auto it = tp.m.find(key);
+    if (it == tp.m.end()) {
+      Plan p = plan_trotter(n, dbl, TuneOpts{}, &E, steps, final);
+      auto d = std::make_unique<DevPlanBuf>();
+      d->load(p, s->stream);
+      it = tp.m.emplace(key, std::make_pair(std::move(p), std::move(d))).first;
+    }
+    return it->second;
+  };
+  std::vector<double> ang(K + 1), scl(K);
+  auto sk = [&](int64_t k) { return (double(k) + 0.5) * dt / T; };
+  for (int64_t j = 0; j <= K; ++j) {
+    double a = 0.0;
+    if (j < K) a += -(1.0 - sk(k0 + j)) * dt;
+    if (j > 0) a += -(1.0 - sk(k0 + j - 1)) * dt;
+    ang[j] = a;
+  }
+  for (int64_t j = 0; j < K; ++j) scl[j] = -sk(k0 + j) * dt;
+  DBuf dang, dscl;
+  upload(dang, ang, s->stream);
+  upload(dscl, scl, s->stream);
+  if (nfull > 0) {
+    auto& blk = get(S, false);
+    for (int64_t b = 0; b < nfull; ++b)
+      run_passes(*blk.second, blk.first, dbl, s->ptr, nullptr, dang.as<double>() + b * S, dscl.as<double>() + b * S,
+                 nullptr, s->stream);
+  }
+  // the last segment: angle slots K - L .. K (the closing layer is slot L), scales K - L .. K - 1
+  auto& last = get(L, true);
+  run_passes(*last.second, last.first, dbl, s->ptr, nullptr, dang.as<double>() + (K - L), dscl.as<double>() + (K - L),
+             nullptr, s->stream);
+  // dang / dscl are freed when this returns: the passes that read them must be done
+  hipck(hipStreamSynchronize(s->stream), "sync");
+}
+
+// Reduced density matrix of qubits 0..a-1 (or of the rest, the smaller side)
+// as a Gram matrix on the GPU, its eigenvalues on the host.
+double entropy_dev(qs_state* s, int a) {
+  const int n = s->n, b = n - a;
+  const int small = std::min(a, b), big = std::max(a, b);
+  if (small > 10) fail(QS_E_UNSUPPORTED, "entropy needs min(a, n - a) <= 10");
+  const int d = 1 << small;
+  const int64_t K = int64_t(1) << big;
+  const int64_t cols = int64_t(1) << b;  // psi[i * 2^b + j]: i the first a qubits, j the rest
+  // rho_A = M M^dagger (a <= b) or rho_B = M^T conj(M) (a > b): same nonzero spectrum
+  int64_t ars, acs, brs, bcs;
+  if (a <= b) {
+    ars = cols; acs = 1; brs = 1; bcs = cols;
+  } else {
+    ars = 1; acs = cols; brs = cols; bcs = 1;
+  }
+  const int tiles = ((d + 63) / 64) * ((d + 63) / 64);
+  int want = std::max(1, 1024 / tiles);
+  want = (int)std::min<int64_t>(want, std::max<int64_t>(1, K / 64));
+  const int splits = zgemm_splits(K, want);
+  const size_t dd = size_t(d) * d;
+  s->scratch2.ensure((splits + 1) * dd * 16);
+  double* part = s->scratch2.as<double>();
+  double* G = part + 2 * splits * dd;
+  hipck(launch_zgemm(s->dbl(), s->ptr, ars, acs, 0, s->ptr, brs, bcs, 1, d, d, K, want, part, 1.0, 0.0, 0,
+                     s->stream),
+        "Gram matrix");
+  hipck(launch_split_sum(part, splits, (int64_t)dd, G, s->stream), "Gram sum");
+  std::vector<cd> h(dd);
+  hipck(hipMemcpyAsync(h.data(), G, dd * 16, hipMemcpyDeviceToHost, s->stream), "download");
+  hipck(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+  return entropy_of_eigenvalues(hermitian_eigenvalues(d, std::move(h)));
+}
+
+void check_callbacks(const qs_callbacks* cb, const qs_state* s) {
+  if (!cb || cb->every <= 0) return;
+  if (cb->energy && (!cb->energies || cb->energy->n != s->n)) fail(QS_E_INVALID, "energy callback: bad observable or null output");
+  if (cb->entropy_qubits > 0) {
+    if (!cb->entropies) fail(QS_E_INVALID, "entropy callback: null output");
+    if (cb->entropy_qubits >= s->n) fail(QS_E_INVALID, "entropy callback: entropy_qubits must be in [1, n-1]");
+    if (std::min(cb->entropy_qubits, s->n - cb->entropy_qubits) > 10)
+      fail(QS_E_UNSUPPORTED, "entropy needs min(a, n - a) <= 10");
+  }
+  if (cb->entropy_qubits < 0) fail(QS_E_INVALID, "negative entropy_qubits");
+}
+
+void run_callbacks(qs_state* s, const qs_callbacks* cb, int64_t idx) {
+  if (cb->energy) {
+    auto* o = const_cast<qs_obs*>(cb->energy);
+    double* res = expect_result_slot(s, o);
+    expectation_dev(s, o, res);
+    cb->energies[idx] = download_scalar(res, s->stream);
+  }
+  if (cb->entropy_qubits > 0) cb->entropies[idx] = entropy_dev(s, cb->entropy_qubits);
+}
+
+double coeff_norm(const qs_obs* o) {
+  double t = 0.0;
+  for (const PauliTermDev& d : o->terms) t += std::fabs(d.coeff);
+  return t;
+}
+
+// One state-sized device vector viewed as a state (same n, dtype, stream).
+struct VecView {
+  qs_state v;
+  VecView(const qs_state* s, void* p) {
+    v.n = s->n;
+    v.dt = s->dt;
+    v.ptr = p;
+    v.owned = false;
+    v.stream = s->stream;
+  }
+};
+
+// lambda = H(u) y = (1 - u) h0 y + u h1 y, then k = -i lambda (in place)
+void rk_rhs(qs_state* s, qs_obs* h0, qs_obs* h1, void* y, void* k, void* tmp, double u, double* part, double* res) {
+  VecView yv(s, y);
+  pauli_pass(&yv.v, h0, k, res, part);
+  pauli_pass(&yv.v, h1, tmp, res, part);
+  LinComb lc{};
+  lc.nin = 2;
+  lc.in[0] = k;
+  lc.cre[0] = 0.0;
+  lc.cim[0] = -(1.0 - u);
+  lc.in[1] = tmp;
+  lc.cre[1] = 0.0;
+  lc.cim[1] = -u;
+  hipck(launch_lincomb(s->dbl(), k, s->n, lc, s->stream), "lincomb");
+}
+
+}  // namespace
+
+extern "C" {
+
 qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, int32_t order,
                            double* energy_out) {
+  return qs_adiabatic_run_callbacks(s, h1, T, dt, order, nullptr, energy_out);
+}
+
+qs_status qs_adiabatic_run_callbacks(qs_state* s, const qs_obs* h1, double T, double dt, int32_t order,
+                                     const qs_callbacks* cb, double* energy_out) {
   return guard([&] {
     check_state(s);
     if (!h1 || !h1->ising) fail(QS_E_INVALID, "h1 must be an Ising observable");
     if (h1->n != s->n) fail(QS_E_STATE, "observable and state sizes differ");
     if (order != 2) fail(QS_E_UNSUPPORTED, "only the second-order split is implemented");
-    if (!(T > 0) || !(dt > 0) || !std::isfinite(T) || !std::isfinite(dt)) fail(QS_E_INVALID, "T and dt must be > 0");
-    const double kf = T / dt;
-    const int64_t K = (int64_t)std::llround(kf);
-    if (K < 1 || std::fabs(kf - (double)K) > 1e-9 * std::max(1.0, kf)) fail(QS_E_INVALID, "T/dt must be an integer");
-    const int n = s->n;
-    const bool dbl = s->dbl();
-    PhasePoly E = ising_poly(n, h1->J.data(), h1->h.data());
-    // blocks of S steps share passes (the last pass of a step carries the next
-    // step's rotations on its tile bits).  Up to 16 steps form one block; longer
-    // runs replay blocks of 8.  The last segment (the final block or the
-    // remainder) also carries the closing half rotation layer.
-    const int S = (int)(K <= 16 ? K : 8);
-    const int64_t rem = K % S;
-    const int64_t nfull = K / S - (rem ? 0 : 1);  // blocks before the last segment
-    const int L = (int)(rem ? rem : S);           // steps of the last segment
-    Plan block, last;
-    DevPlanBuf dblock, dlast;
-    if (nfull > 0) {
-      block = plan_trotter(n, dbl, TuneOpts{}, &E, S);
-      dblock.load(block, s->stream);
+    const int64_t K = step_count(T, dt);
+    check_callbacks(cb, s);
+    const PhasePoly E = ising_poly(s->n, h1->J.data(), h1->h.data());
+    TrotterPlans tp;
+    const int64_t every = (cb && cb->every > 0) ? cb->every : K;
+    int64_t idx = 0;
+    for (int64_t k0 = 0; k0 < K; k0 += every) {
+      const int64_t k1 = std::min(K, k0 + every);
+      trotter_segment(s, E, T, dt, k0, k1, tp);
+      if (cb && cb->every > 0 && k1 - k0 == every) run_callbacks(s, cb, idx++);
     }
-    last = plan_trotter(n, dbl, TuneOpts{}, &E, L, true);
-    dlast.load(last, s->stream);
-    // merged RX angles and phase scales
-    std::vector<double> ang(K + 1), scl(K);
-    auto sk = [&](int64_t k) { return (double(k) + 0.5) * dt / T; };
-    for (int64_t k = 0; k <= K; ++k) {
-      double a = 0.0;
-      if (k < K) a += -(1.0 - sk(k)) * dt;
-      if (k > 0) a += -(1.0 - sk(k - 1)) * dt;
-      ang[k] = a;
-    }
-    for (int64_t k = 0; k < K; ++k) scl[k] = -sk(k) * dt;
-    DBuf dang, dscl;
-    upload(dang, ang, s->stream);
-    upload(dscl, scl, s->stream);
-    for (int64_t b = 0; b < nfull; ++b)
-      run_passes(dblock, block, dbl, s->ptr, nullptr, dang.as<double>() + b * S, dscl.as<double>() + b * S, nullptr,
-                 s->stream);
-    // the last segment: angle slots K - L .. K (the closing layer is slot L), scales K - L .. K - 1
-    run_passes(dlast, last, dbl, s->ptr, nullptr, dang.as<double>() + (K - L), dscl.as<double>() + (K - L), nullptr,
-               s->stream);
     if (energy_out) {
       auto* o = const_cast<qs_obs*>(h1);
       double* res = expect_result_slot(s, o);
@@ -1097,6 +1384,152 @@ qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, i
   });
 }
 
+qs_status qs_entanglement_entropy(const qs_state* cs, int32_t a, double* out) {
+  return guard([&] {
+    check_state(cs);
+    if (!out) fail(QS_E_INVALID, "null output");
+    if (a < 1 || a >= cs->n) fail(QS_E_INVALID, "a must be in [1, n-1]");
+    *out = entropy_dev(const_cast<qs_state*>(cs), a);
+  });
+}
+
+qs_status qs_evolve(qs_state* s, const qs_obs* ch0, const qs_obs* ch1, double T, double dt, int32_t solver,
+                    const qs_callbacks* cb) {
+  return guard([&] {
+    check_state(s);
+    if (!ch0 || !ch1) fail(QS_E_INVALID, "null observable");
+    if (ch0->n != s->n || ch1->n != s->n) fail(QS_E_STATE, "observables and state sizes differ");
+    if (solver != QS_SOLVER_EXP && solver != QS_SOLVER_RK4 && solver != QS_SOLVER_RK45)
+      fail(QS_E_INVALID, "unknown solver");
+    const int64_t K = step_count(T, dt);
+    check_callbacks(cb, s);
+    auto* h0 = const_cast<qs_obs*>(ch0);
+    auto* h1 = const_cast<qs_obs*>(ch1);
+    h0->to_device(s->stream);
+    h1->to_device(s->stream);
+    const int n = s->n;
+    const bool dbl = s->dbl();
+    const int64_t every = (cb && cb->every > 0) ? cb->every : 0;
+    int64_t idx = 0;
+    auto after_step = [&](int64_t k) {
+      if (every && (k + 1) % every == 0) run_callbacks(s, cb, idx++);
+    };
+    if (solver == QS_SOLVER_EXP) {
+      if (n > 12) fail(QS_E_UNSUPPORTED, "the exp solver builds a dense 2^n x 2^n matrix: n <= 12");
+      const int64_t D = int64_t(1) << n;
+      const size_t mat = size_t(D) * D * 2;  // doubles
+      DBuf bH, bP, bQ, bT;
+      bH.ensure(mat * 8);
+      bP.ensure(mat * 8);
+      bQ.ensure(mat * 8);
+      bT.ensure(size_t(D) * (dbl ? 16 : 8));
+      double* H = bH.as<double>();
+      const double c0 = coeff_norm(h0), c1 = coeff_norm(h1);
+      for (int64_t k = 0; k < K; ++k) {
+        const double u = (double(k) + 0.5) * dt / T;
+        hipck(launch_zero(H, (int64_t)mat, s->stream), "zero");
+        hipck(launch_dense_h_add(H, n, h0->dflips.as<uint64_t>(), h0->dgoff.as<int32_t>(), h0->dterms.as<PauliTermDev>(),
+                                 (int)h0->flips.size(), 1.0 - u, s->stream),
+              "dense H0");
+        hipck(launch_dense_h_add(H, n, h1->dflips.as<uint64_t>(), h1->dgoff.as<int32_t>(), h1->dterms.as<PauliTermDev>(),
+                                 (int)h1->flips.size(), u, s->stream),
+              "dense H1");
+        // exp(-i dt H) = (T_m(X))^(2^q), X = -i dt H / 2^q with ||X|| <= 1/2
+        // (||H|| <= sum |c_t| of the Pauli terms), T_m the Taylor polynomial
+        // of degree m with ||X||^(m+1) / (m+1)! <= 1e-18, in Horner form
+        const double th = dt * ((1.0 - u) * c0 + u * c1);
+        int q = 0;
+        while (std::ldexp(th, -q) > 0.5) ++q;
+        const double x = std::ldexp(th, -q);
+        int m = 1;
+        double rem = x * x / 2.0;  // x^(m+1) / (m+1)!
+        while (rem > 1e-18 && m < 40) {
+          ++m;
+          rem *= x / (m + 1);
+        }
+        double* P = bP.as<double>();
+        double* Q = bQ.as<double>();
+        hipck(launch_identity(P, n, s->stream), "identity");
+        const double sc = -dt * std::ldexp(1.0, -q);
+        for (int j = m; j >= 1; --j) {  // P <- I + X P / j
+          hipck(launch_zgemm(true, H, D, 1, 0, P, D, 1, 0, (int)D, (int)D, D, 1, Q, 0.0, sc / j, 1, s->stream),
+                "Taylor step");
+          std::swap(P, Q);
+        }
+        for (int r = 0; r < q; ++r) {  // squaring
+          hipck(launch_zgemm(true, P, D, 1, 0, P, D, 1, 0, (int)D, (int)D, D, 1, Q, 1.0, 0.0, 0, s->stream), "square");
+          std::swap(P, Q);
+        }
+        hipck(launch_matvec(dbl, P, s->ptr, bT.p, n, s->stream), "U psi");
+        hipck(hipMemcpyAsync(s->ptr, bT.p, size_t(D) * (dbl ? 16 : 8), hipMemcpyDeviceToDevice, s->stream), "copy");
+        after_step(k);
+      }
+      hipck(hipStreamSynchronize(s->stream), "sync");
+      return;
+    }
+    // Runge-Kutta: tableau (c, a, b) of the classical RK4 or of Dormand-Prince 5(4)
+    static const double rk4_c[4] = {0.0, 0.5, 0.5, 1.0};
+    static const double rk4_a[4][6] = {{0}, {0.5}, {0.0, 0.5}, {0.0, 0.0, 1.0}};
+    static const double rk4_b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+    static const double dp_c[6] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0};
+    static const double dp_a[6][6] = {{0},
+                                      {1.0 / 5},
+                                      {3.0 / 40, 9.0 / 40},
+                                      {44.0 / 45, -56.0 / 15, 32.0 / 9},
+                                      {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729},
+                                      {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656}};
+    static const double dp_b[6] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84};
+    const bool rk4 = solver == QS_SOLVER_RK4;
+    const int S = rk4 ? 4 : 6;
+    const double* cc = rk4 ? rk4_c : dp_c;
+    const double* bb = rk4 ? rk4_b : dp_b;
+    auto aa = [&](int j, int l) { return rk4 ? rk4_a[j][l] : dp_a[j][l]; };
+    const size_t vb = s->bytes();
+    std::vector<std::unique_ptr<DBuf>> kv(S);
+    for (auto& b : kv) {
+      b = std::make_unique<DBuf>();
+      b->ensure(vb);
+    }
+    DBuf by, btmp, bpart;
+    by.ensure(vb);
+    btmp.ensure(vb);
+    const size_t pd = std::max(pauli_scratch_doubles(h0), pauli_scratch_doubles(h1)) + 8;
+    bpart.ensure(pd * 8);
+    double* part = bpart.as<double>();
+    double* res = part + pd - 8;
+    for (int64_t k = 0; k < K; ++k) {
+      const double t = double(k) * dt;
+      for (int j = 0; j < S; ++j) {
+        void* y = s->ptr;
+        if (j > 0) {  // y = psi + dt sum_l a_jl k_l
+          LinComb lc{};
+          lc.in[lc.nin] = s->ptr;
+          lc.cre[lc.nin++] = 1.0;
+          for (int l = 0; l < j; ++l)
+            if (aa(j, l) != 0.0) {
+              lc.in[lc.nin] = kv[l]->p;
+              lc.cre[lc.nin++] = dt * aa(j, l);
+            }
+          hipck(launch_lincomb(dbl, by.p, n, lc, s->stream), "stage input");
+          y = by.p;
+        }
+        rk_rhs(s, h0, h1, y, kv[j]->p, btmp.p, (t + cc[j] * dt) / T, part, res);
+      }
+      LinComb lc{};  // psi <- psi + dt sum_l b_l k_l
+      lc.in[lc.nin] = s->ptr;
+      lc.cre[lc.nin++] = 1.0;
+      for (int l = 0; l < S; ++l)
+        if (bb[l] != 0.0) {
+          lc.in[lc.nin] = kv[l]->p;
+          lc.cre[lc.nin++] = dt * bb[l];
+        }
+      hipck(launch_lincomb(dbl, s->ptr, n, lc, s->stream), "step");
+      after_step(k);
+    }
+    hipck(hipStreamSynchronize(s->stream), "sync");
+  });
+}
+
 // ---------------------------------------------------------------- adjoint
 qs_status qs_adjoint(qs_circuit* c, const double* params, const qs_obs* H, qs_state* psi, qs_state* lam,
                      double* grad_out, double* energy_out) {
@@ -1104,6 +1537,7 @@ qs_status qs_adjoint(qs_circuit* c, const double* params, const qs_obs* H, qs_st
     if (!c || !H) fail(QS_E_INVALID, "null argument");
     check_state(psi);
     check_state(lam);
+    if (c->dens) fail(QS_E_UNSUPPORTED, "the adjoint needs a state-vector circuit, not a density-matrix one");
     if (psi == lam || psi->ptr == lam->ptr) fail(QS_E_INVALID, "psi and lambda must be distinct states");
     if (c->hc.n != psi->n || lam->n != psi->n || lam->dt != psi->dt || H->n != psi->n)
       fail(QS_E_STATE, "circuit, observable and states must have the same n and dtype");
@@ -1167,6 +1601,8 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
     if (count < 1) fail(QS_E_INVALID, "count must be >= 1");
     if (!circs || !obs) fail(QS_E_INVALID, "null circuits or observables");
     check_dtype(dt);
+    for (int i = 0; i < count; ++i)
+      if (circs[i] && circs[i]->dens) fail(QS_E_UNSUPPORTED, "batches take state-vector circuits only");
     check_device();
     auto b = std::make_unique<qs_batch>();
     b->count = count;
@@ -1410,6 +1846,7 @@ uint64_t circuit_hash(const HostCircuit& hc) {
     mix(&g.is_rot, sizeof g.is_rot);
     mix(&g.pauli, sizeof g.pauli);
     mix(&g.pidx, sizeof g.pidx);
+    mix(&g.rsign, sizeof g.rsign);
     if (!g.mat.empty()) mix(g.mat.data(), g.mat.size() * sizeof(g.mat[0]));
   }
   return h;

@@ -148,4 +148,42 @@ hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 int sample_nblocks(int n);
 int sample_nchunks(int n);
 
+// Density matrices (density.hip): an n-qubit rho stored as a 2n-qubit vector,
+// rho[r][c] at r * 2^n + c.
+// rho = |psi><psi| (psi has 2^n amplitudes, rho 4^n)
+hipError_t launch_outer(bool dbl, void* rho, const void* psi, int n, hipStream_t s);
+// out[0] (device) = Re Tr(P rho), P = the Pauli groups (flip masks, term
+// ranges goff[g]..goff[g+1]); ngroups = 0 gives Re Tr(rho).  partials: kGridMax doubles.
+hipError_t launch_dens_pauli(bool dbl, const void* rho, int n, const uint64_t* flips, const int32_t* goff,
+                             const PauliTermDev* terms, int ngroups, double* partials, double* out,
+                             hipStream_t s);
+
+// Time evolution and reduced density matrices (evolution.hip).
+// out = sum_l c_l in_l over 2^n amplitudes (c_l complex, float64 arithmetic);
+// out may be one of the inputs.
+constexpr int kLinCombMax = 8;
+struct LinComb {
+  const void* in[kLinCombMax];
+  double cre[kLinCombMax], cim[kLinCombMax];
+  int nin;
+};
+hipError_t launch_lincomb(bool dbl, void* out, int n, const LinComb& lc, hipStream_t s);
+// H (dense 2^n x 2^n complex128, row-major) += scale * sum of the Pauli groups
+hipError_t launch_dense_h_add(double* H, int n, const uint64_t* flips, const int32_t* goff, const PauliTermDev* terms,
+                              int ngroups, double scale, hipStream_t s);
+// out (complex128) = alpha * op(A) op(B) (+ I), op(A)(i,j) = a[i ars + j acs]
+// (conjugated if conja), op(B)(j,k) = b[j brs + k bcs]; M x N, contraction K
+// split into zgemm_splits(K, nsplit) chunks, chunk c written to the slab
+// out + c M N (complex entries); a, b in the state precision (dbl) or float64.
+hipError_t launch_zgemm(bool dbl, const void* a, int64_t ars, int64_t acs, int conja, const void* b, int64_t brs,
+                        int64_t bcs, int conjb, int M, int N, int64_t K, int nsplit, double* out, double alpha_re,
+                        double alpha_im, int add_identity, hipStream_t s);
+int zgemm_splits(int64_t K, int nsplit);
+// out[i] = sum of the nsplit slabs (count complex128 entries each), in order
+hipError_t launch_split_sum(const double* part, int nsplit, int64_t count, double* out, hipStream_t s);
+// P = identity (2^n x 2^n complex128)
+hipError_t launch_identity(double* P, int n, hipStream_t s);
+// y = U x, U dense 2^n x 2^n complex128; x, y in the state precision
+hipError_t launch_matvec(bool dbl, const double* U, const void* x, void* y, int n, hipStream_t s);
+
 }  // namespace qs

@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_tile(typename CT<R>::C* __restrict__ ps
           break;
         }
         case OP_ROT: {
-          const double th = (TWO ? -1.0 : 1.0) * params[op.pidx];
+          const double th = (TWO ? -1.0 : 1.0) * op.sign * params[op.pidx];
           if (TWO && op.gslot >= 0) {
             const double v = block_sum(rot_grad_partial(t1, t2, M, op.b[0], op.cin, op.pauli), red);
             if (tid == 0) gpart[(int64_t)op.gslot * kGradStride + blockIdx.x * 4] += v;
@@ -2215,7 +2215,7 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
     const double* par = a.params + in.param_base;
     for (int o = tid; o < in.nops; o += kThreads) {
       const TileOp op = a.dp.ops[in.ops_base + o];
-      if (op.kind == OP_ROT && op.mat >= 0) rot_fill(matc + in.mat_base + op.mat, op.pauli, par[op.pidx]);
+      if (op.kind == OP_ROT && op.mat >= 0) rot_fill(matc + in.mat_base + op.mat, op.pauli, op.sign * par[op.pidx]);
     }
     for (int64_t x = tid; x < N; x += kThreads) psi[x] = mk<C>(x == 0 ? 1.0 : 0.0, 0.0);
     double* gp = a.gpart + (int64_t)in.slot_base * 4;
@@ -2296,7 +2296,7 @@ __global__ void k_rot_mats(const TileOp* __restrict__ ops, int nops, const doubl
   const TileOp op = ops[i];
   if (op.kind != OP_ROT || op.mat < 0) return;
   double s, c;
-  sincos(0.5 * params[op.pidx], &s, &c);
+  sincos(0.5 * op.sign * params[op.pidx], &s, &c);
   C* m = matc + op.mat;
   for (int inv = 0; inv < 2; ++inv) {
     const double si = inv ? -s : s;

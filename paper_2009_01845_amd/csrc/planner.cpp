@@ -78,6 +78,7 @@ struct BitGate {
   std::vector<cd> mat;
   char pauli = 0;
   int pidx = -1;
+  int rsign = 1;
   double cphase = 0.0;
   std::vector<Term> terms;
   uint64_t nmask = 0;  // bits where the gate is not diagonal
@@ -182,6 +183,7 @@ BitGate to_bits(const Gate& g, int n, const std::vector<int>& phys, const TuneOp
     b.kind = BK_ROT;
     b.pauli = g.pauli;
     b.pidx = g.pidx;
+    b.rsign = g.rsign;
     if (g.pauli == 'Z') b.dmask |= 1ull << b.tb[0];
     else b.nmask |= 1ull << b.tb[0];
     return b;
@@ -752,6 +754,7 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
       }
       if (r.kind == OP_ROT) {
         op.pidx = bg.pidx;
+        op.sign = bg.rsign;
         op.pauli = bg.pauli == 'X' ? 1 : bg.pauli == 'Y' ? 2 : 3;
         if (bg.pidx >= 0) {
           if (ngrad >= kMaxGradPerPass) throw std::runtime_error("planner: too many parameters in one pass");

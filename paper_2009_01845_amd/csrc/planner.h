@@ -18,6 +18,7 @@ struct Gate {
   bool is_rot = false;
   char pauli = 0;
   int pidx = -1;
+  int rsign = 1;        // rotations: theta = rsign * params[pidx]
   std::vector<cd> mat;  // 2^k x 2^k row-major, MAT gates only
   // a diagonal exp(i scales[scale_slot] * E(x)) with E a polynomial owned by
   // the caller (adiabatic steps); k and the target list are unused

@@ -35,7 +35,7 @@ struct TileOp {
   int32_t mat;       // offset (complex entries) into the matrix pool; -1 if none
   int32_t pidx;      // OP_ROT: parameter index
   int32_t pauli;     // OP_ROT: 1 = X, 2 = Y, 3 = Z
-  int32_t sign;      // OP_ROT: +1 forward, -1 inverse
+  int32_t sign;      // OP_ROT: theta = sign * params[pidx] (sign = +-1)
   int32_t aux;       // OP_PHASE: phase record index; OP_DIAG: offset into diag pool;
                      // OP_ROT with a gradient slot: its index among the pass's gradient ops
   int32_t gslot;     // adjoint: gradient slot of this op (-1 if none)
