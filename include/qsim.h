@@ -207,6 +207,21 @@ qs_status qs_obs_destroy(qs_obs* o);
 qs_status qs_expectation(const qs_state* s, const qs_obs* o, double* out);
 /* Same, written to a device double; stays on the stream (no host sync). */
 qs_status qs_expectation_async(const qs_state* s, const qs_obs* o, double* dev_out);
+/* Same result as qs_expectation_async, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): this call performs no hipMalloc, hipFree or other
+ * allocation.  Its partial sums go to a fixed workspace of the library, one
+ * per GPU (about 1 MiB, held until the process ends), which fits an
+ * observable with at most 64 reduction slots (one for all diagonal terms, one
+ * per tile set and one per far flip group); a larger observable returns
+ * QS_E_INVALID.  The observable's own tables must already be on the device:
+ * one qs_expectation or qs_expectation_async call with it uploads them;
+ * otherwise QS_E_STATE.  dev_out is a device double written on s's stream
+ * (no host sync).  Every call on one GPU shares that workspace, and the
+ * kernels clear what they accumulate into at the start of each call: calls
+ * that overlap on one GPU (other streams, other threads) race and may return
+ * wrong values; serialise them. */
+qs_status qs_expectation_noalloc(const qs_state* s, const qs_obs* o, double* dev_out);
 /* <psi|psi> in float64. */
 qs_status qs_norm2(const qs_state* s, double* out);
 

@@ -74,6 +74,7 @@ SIGNATURES = {
     "qs_obs_destroy": (_st, [_p]),
     "qs_expectation": (_st, [_p, _p, _f64p]),
     "qs_expectation_async": (_st, [_p, _p, _p]),
+    "qs_expectation_noalloc": (_st, [_p, _p, _p]),
     "qs_norm2": (_st, [_p, _f64p]),
     "qs_sample": (_st, [_p, _i32, _i32p, _i64, _u64, _f64p, C.POINTER(C.c_int64)]),
     "qs_adiabatic_run": (_st, [_p, _p, C.c_double, C.c_double, _i32, _f64p]),

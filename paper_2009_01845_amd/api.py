@@ -250,6 +250,10 @@ def expectation_async(h, o, dev_out: int):
     check(lib().qs_expectation_async(h, o, C.c_void_p(int(dev_out))))
 
 
+def expectation_noalloc(h, o, dev_out: int):
+    check(lib().qs_expectation_noalloc(h, o, C.c_void_p(int(dev_out))))
+
+
 def norm2(h) -> float:
     v = C.c_double()
     check(lib().qs_norm2(h, C.byref(v)))

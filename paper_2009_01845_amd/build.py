@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqsim.so")
 
-SOURCES = ["api.cpp", "planner.cpp", "linalg.cpp", "kernels.hip", "density.hip", "evolution.hip"]
+SOURCES = ["api.cpp", "planner.cpp", "linalg.cpp", "kernels.hip", "density.hip", "evolution.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1083,6 +1083,31 @@ qs_status qs_expectation_async(const qs_state* cs, const qs_obs* co, double* dev
   });
 }
 
+qs_status qs_expectation_noalloc(const qs_state* cs, const qs_obs* co, double* dev_out) {
+  return guard([&] {
+    check_state(cs);
+    if (!co || !dev_out) fail(QS_E_INVALID, "null argument");
+    auto* s = const_cast<qs_state*>(cs);
+    auto* o = const_cast<qs_obs*>(co);
+    if (o->n != s->n) fail(QS_E_STATE, "observable and state sizes differ");
+    if (o->flips.empty()) {
+      hipck(launch_zero(dev_out, 1, s->stream), "zero");
+      return;
+    }
+    if (!o->dev_ok)
+      fail(QS_E_STATE,
+           "the observable's tables are not on the device: one qs_expectation or qs_expectation_async call with it "
+           "uploads them");
+    const int nslot = obs_slots(o);
+    if (nslot > kNoAllocMaxSlots || (int64_t)pauli_scratch_doubles(o) > kNoAllocScratchDoubles)
+      fail(QS_E_INVALID, "observable needs " + std::to_string(nslot) + " reduction slots; the fixed workspace holds " +
+                             std::to_string(kNoAllocMaxSlots));
+    double* ws = nullptr;
+    hipck(noalloc_scratch(&ws), "hipGetSymbolAddress(scratch)");
+    pauli_pass(s, o, nullptr, dev_out, ws);
+  });
+}
+
 qs_status qs_norm2(const qs_state* cs, double* out) {
   return guard([&] {
     check_state(cs);

@@ -28,6 +28,14 @@ struct DevPlan {
 constexpr int kGridMax = 2048;  // fixed upper bound on streaming grids (deterministic reductions)
 constexpr int kGradStride = kGridMax * 4;  // adjoint partials: one slot per (block, wave)
 
+// Fixed device workspace of the no-allocation entry points (noalloc.hip):
+// room for the partial sums of an observable with up to kNoAllocMaxSlots
+// reduction slots (diagonal polynomial, tile sets, far groups).
+constexpr int kNoAllocMaxSlots = 64;
+constexpr int64_t kNoAllocScratchDoubles = int64_t(kNoAllocMaxSlots + 1) * kGridMax + kNoAllocMaxSlots + 8;
+// Device address of this device's workspace (looked up once per device).
+hipError_t noalloc_scratch(double** out);
+
 int tile_grid(const PassGeom& g);
 
 // One tiled pass.  psi2 != nullptr selects the two-state (adjoint) kernel:
