@@ -163,10 +163,28 @@ def sweep(n: int, dt: str, only: str | None):
     for _ in range(5):
         y.copy_(st.tensor)
     torch.cuda.synchronize()
-    copy_gbs = bytes_pass / ((time.perf_counter() - t) / 5) / 1e9
+    torch_copy_gbs = bytes_pass / ((time.perf_counter() - t) / 5) / 1e9
     del y
     torch.cuda.empty_cache()
-    print(json.dumps({"case": "device_copy", "GB/s": copy_gbs}), flush=True)
+    # the library's streaming copy kernel (non-temporal 16-byte accesses, eight
+    # in flight per thread): the measured streaming ceiling of this machine
+    st2 = api.State(n, dt)
+    for _ in range(2):
+        api.state_copy(st2.h, st.h)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        api.state_copy(st2.h, st.h)
+    torch.cuda.synchronize()
+    copy_gbs = bytes_pass / ((time.perf_counter() - t) / 5) / 1e9
+    del st2
+    torch.cuda.empty_cache()
+    print(json.dumps({"case": "device_copy", "GB/s": copy_gbs, "torch_copy_GB/s": torch_copy_gbs,
+                      "frac_of_8TBs": copy_gbs / HBM_PEAK_GBS}), flush=True)
+    # a read-only pass: the float64 norm reduction reads every amplitude once
+    ms = _ev_ms(lambda: st.norm2(), 5)
+    print(json.dumps({"case": "read_norm2", "ms": ms, "GB/s": (1 << n) * b / (ms / 1e3) / 1e9,
+                      "frac_of_8TBs": (1 << n) * b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}), flush=True)
     Q = lambda bit: n - 1 - bit  # noqa: E731  (qubit holding index bit `bit`)
     hu = lambda k: qsynth.haar_unitary(1 << k, rng)  # noqa: E731
     cases = {}
@@ -224,6 +242,227 @@ def sweep(n: int, dt: str, only: str | None):
         print(json.dumps(row), flush=True)
 
 
+def _ev_ms(fn, reps: int, warm: int = 2) -> float:
+    """Median device time of fn over reps runs (torch events on the current
+    stream; fn enqueues on that stream)."""
+    import statistics
+
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return statistics.median(out)
+
+
+def rows(only: str | None):
+    """The measurement rows of the workloads, one JSON line each: the 10-qubit
+    circuit eager and as a graph (M1), QFT-28 in both precisions (M2), the
+    gradient workload at 20 qubits and the same ansatz at 26/28/30 (M3), the
+    512-instance batch against instance-by-instance launches (M4), the 24-qubit
+    adiabatic run (M5), sampling against shots (M6) and the 30-qubit circuits
+    in both precisions (M7).  Device times are medians of hipEvent pairs on the
+    launch stream."""
+    import numpy as np
+    import torch
+
+    import qsynth
+    from paper_2009_01845_amd import api
+    torch.cuda.set_device(0)
+
+    def emit(row):
+        print(json.dumps(row), flush=True)
+
+    def want(name):
+        return only is None or only in name
+
+    if want("M1"):
+        n, spec, params, terms = qsynth.variational_10q(0)
+        c = api.Circuit.from_spec(n, spec)
+        H = api.Observable.pauli_sum(n, terms)
+        st = api.State(n, "c128")
+        dp = torch.tensor(params, dtype=torch.float64, device="cuda")
+        eo = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+        def once():
+            st.set_basis(0)
+            api.circuit_run(c.h, st.h, dp.data_ptr(), params_on_device=True)
+            api.expectation_async(st.h, H.h, eo.data_ptr())
+        eager = _ev_ms(once, 50)
+        once()
+        torch.cuda.synchronize()
+        e_eager = float(eo.item())
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            st_g = api.State(n, "c128", stream=s.cuda_stream)
+            once_g = lambda: (api.state_set_basis(st_g.h, 0),  # noqa: E731
+                              api.circuit_run(c.h, st_g.h, dp.data_ptr(), params_on_device=True),
+                              api.expectation_async(st_g.h, H.h, eo.data_ptr()))
+            once_g()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                once_g()
+        torch.cuda.synchronize()
+        same = True
+        for _ in range(5):  # each replay checked against the eager result
+            eo.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            same &= float(eo.item()) == e_eager
+        graph = _ev_ms(lambda: g.replay(), 50)
+        emit({"row": "M1", "workload": "10-qubit depth-20 RY/RZ/CZ, complex128, run + energy",
+              "gates": c.info()[0], "eager_us": eager * 1e3, "graph_us": graph * 1e3,
+              "graph_replays_equal_eager": bool(same), "gates_per_s_graph": c.info()[0] / (graph / 1e3)})
+        del g, st_g
+
+    if want("M2"):
+        n = 28
+        for dt in ("c64", "c128"):
+            q = api.Circuit.from_spec(n, qsynth.qft(n))
+            st = api.State(n, dt)
+            st.set_plus()
+            ms = _ev_ms(lambda: q.run(st), 5)
+            b = 8 if dt == "c64" else 16
+            npass = q.info()[1]
+            gbs = npass * 2 * (1 << n) * b / (ms / 1e3) / 1e9
+            emit({"row": "M2", "workload": f"QFT-{n} {dt}", "ms": ms, "gates": q.info()[0], "passes": npass,
+                  "gates_per_s": q.info()[0] / (ms / 1e3), "GB/s": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS})
+            del st, q
+            torch.cuda.empty_cache()
+
+    if want("M3"):
+        for n in (20, 26, 28, 30):
+            _, spec, params, terms = qsynth.gradient_20q(seed=0, n=n, layers=10)
+            c = api.Circuit.from_spec(n, spec)
+            H = api.Observable.pauli_sum(n, terms)
+            st, lam = api.State(n, "c64"), api.State(n, "c64")
+            eo = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+            def fwd():
+                st.set_basis(0)
+                c.run(st, params)
+                api.expectation_async(st.h, H.h, eo.data_ptr())
+            t_f = _ev_ms(fwd, 5)
+            tb = []
+            for _ in range(4):
+                fwd()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                api.adjoint(c.h, params, H.h, st.h, lam.h, c.nparams)
+                tb.append((time.perf_counter() - t0) * 1e3)
+            t_b = float(np.median(tb[1:]))
+            emit({"row": "M3", "workload": f"{n}-qubit 10 x (RY all + CZ ring), complex64, H = ZZ ring + 0.5 X",
+                  "params": c.nparams, "fwd_ms": t_f, "bwd_ms": t_b, "bwd_over_fwd": t_b / t_f,
+                  "total_over_fwd": (t_f + t_b) / t_f, "note": "bwd timed on the host around a synchronising call"})
+            del st, lam
+            torch.cuda.empty_cache()
+
+    if want("M4"):
+        insts = qsynth.batch_instances(seed=0)
+        circs = [api.Circuit.from_spec(m, spec) for m, spec, _, _ in insts]
+        obs = [api.Observable.pauli_sum(m, terms) for m, _, _, terms in insts]
+        bparams = np.concatenate([p for _, _, p, _ in insts])
+        b = api.Batch(circs, obs, "c64")
+        b.run(bparams)
+        b.run(bparams)
+        reps = 5
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.run(bparams)
+        t_batch = (time.perf_counter() - t0) / reps
+        b.run(bparams, want_grads=False)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.run(bparams, want_grads=False)
+        t_fwd = (time.perf_counter() - t0) / reps
+        # instance by instance: eager launches of run + adjoint per circuit
+        states = [(api.State(m, "c64"), api.State(m, "c64")) for m, _, _, _ in insts]
+        off = np.cumsum([0] + [p.size for _, _, p, _ in insts])
+
+        def eager():
+            for i, (m, _, p, _) in enumerate(insts):
+                ps, ls = states[i]
+                ps.set_basis(0)
+                circs[i].run(ps, p)
+                api.adjoint(circs[i].h, p, obs[i].h, ps.h, ls.h, circs[i].nparams)
+        eager()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eager()
+        torch.cuda.synchronize()
+        t_eager = time.perf_counter() - t0
+        gates = sum(cc.info()[0] for cc in circs)
+        emit({"row": "M4", "workload": "512 variational instances, n ~ U{8..18}, depth ~ U{4..12}, complex64",
+              "replay_ms": t_batch * 1e3, "replay_energies_only_ms": t_fwd * 1e3,
+              "instances_per_s": len(insts) / t_batch, "forward_gates_per_s": gates / t_batch,
+              "eager_instance_by_instance_ms": t_eager * 1e3, "speedup_vs_eager": t_eager / t_batch,
+              "gates": gates, "params": int(off[-1])})
+        del b, states
+
+    if want("M5"):
+        na, Ja, ha, T, dta = qsynth.adiabatic_24q(0)
+        st = api.State(na, "c128")
+        I = api.Observable.ising(na, Ja, ha)
+        st.set_plus()
+        api.adiabatic_run(st.h, I.h, T, dta)
+        st.set_plus()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e = api.adiabatic_run(st.h, I.h, T, dta)
+        t = time.perf_counter() - t0
+        K = int(round(T / dta))
+        emit({"row": "M5", "workload": f"adiabatic {na} qubits complex128, T={T}, dt={dta}", "s": t,
+              "ms_per_step": t * 1e3 / K, "energy": e,
+              "overlap_ground": float(st.tensor[int(np.argmin(_ising_e_gpu(Ja, ha, na)))].abs().item() ** 2),
+              "state_MiB": (16 << na) / 2 ** 20, "note": "state smaller than the 256 MB last-level cache"})
+        del st
+        torch.cuda.empty_cache()
+
+    if want("M6"):
+        for n in (20, 24, 28, 30):
+            c = api.Circuit.from_spec(n, [qsynth.gate("H", (q,)) for q in range(n)])
+            st = api.State(n, "c64")
+            t_gate = _ev_ms(lambda: (st.set_basis(0), c.run(st)), 3)
+            for shots in (100, 10_000, 1_000_000):
+                def samp():
+                    api.sample(st.h, list(range(n)), shots, seed=1)
+                t_s = _ev_ms(samp, 3, warm=1)
+                emit({"row": "M6", "workload": f"H on {n} qubits, measure all, complex64", "shots": shots,
+                      "gates_ms": t_gate, "sample_ms": t_s, "shots_per_s": shots / (t_s / 1e3),
+                      "read_GB/s": (8 << n) / (t_s / 1e3) / 1e9})
+            del st
+            torch.cuda.empty_cache()
+
+    if want("M7"):
+        n = 30
+        _, vspec, vparams, _ = qsynth.gradient_20q(seed=0, n=n, layers=10)
+        circuits = {"QFT-30": (qsynth.qft(n), None), "variational-30": (vspec, vparams),
+                    "random-30": (qsynth.random_layers(n, 20, 7), None)}
+        for dt in ("c64", "c128"):
+            st = api.State(n, dt)
+            b = 8 if dt == "c64" else 16
+            for name, (spec, par) in circuits.items():
+                c = api.Circuit.from_spec(n, spec)
+                st.set_plus()
+                ms = _ev_ms(lambda: c.run(st, par), 3, warm=1)
+                npass = c.info()[1]
+                gbs = npass * 2 * (1 << n) * b / (ms / 1e3) / 1e9
+                emit({"row": "M7", "workload": f"{name} {dt}", "ms": ms, "gates": c.info()[0], "passes": npass,
+                      "gates_per_s": c.info()[0] / (ms / 1e3), "GB/s": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS})
+            del st
+            torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,11 +479,16 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="per-kernel-kind table instead of the step (one line per case)")
     ap.add_argument("--sweep-dtype", default="c64")
     ap.add_argument("--sweep-only", default=None, help="run the sweep cases whose name contains this text")
+    ap.add_argument("--rows", action="store_true", help="the measurement rows M1-M7, one JSON line each")
+    ap.add_argument("--rows-only", default=None, help="rows whose name contains this text (e.g. M4)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         sys.exit("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)")
     if args.sweep:
         sweep(args.n, args.sweep_dtype, args.sweep_only)
+        return
+    if args.rows:
+        rows(args.rows_only)
         return
 
     import numpy as np

@@ -65,13 +65,18 @@ typedef struct qs_batch qs_batch;
  *              2..5 = merge runs of gates into k-qubit matrices).
  *   use_mfma   -1 auto, 0 never, 1 apply 4- and 5-qubit fused blocks with
  *              matrix-core (MFMA) instructions.
- *   low_bits   L: lowest index bits always inside a tile (0 = auto). */
+ *   low_bits   L: lowest index bits always inside a tile (0 = auto).
+ *   lane_ops   1: register stages also take uncontrolled one-qubit gates on
+ *              the four lowest tile bits outside their registers, applied
+ *              across lanes with DPP moves (fewer stages, more arithmetic);
+ *              0 (default): register stages only. */
 typedef struct qs_tune {
   int32_t tile_bits;
   int32_t fuse_k;
   int32_t use_mfma;
   int32_t low_bits;
-  int32_t reserved[4];
+  int32_t lane_ops;
+  int32_t reserved[3];
 } qs_tune;
 
 const char* qs_version(void);
@@ -311,12 +316,19 @@ qs_status qs_adjoint(qs_circuit* c, const double* params, const qs_obs* H, qs_st
                      qs_state* lambda, double* grad_out, double* energy_out);
 
 /* ------------------------------------------------------------------- batch
- * Many small circuits (each with its own n, parameters and observable) run
- * in one persistent launch; each instance starts from |0..0>.  The first
- * run captures a HIP graph that later runs replay after uploading new
- * parameters.  params_packed holds every instance's parameters back to back
- * in instance order; energies gets count doubles; grads (may be NULL) gets
- * the gradients packed like params. */
+ * Many small circuits (each with its own n <= 24, parameters and diagonal
+ * observable) evaluated together; each instance starts from |0..0>.  The
+ * work runs level by level: one launch applies pass k of every instance that
+ * has it, one workgroup per tile of each instance, so a large instance is
+ * spread over as many workgroups as it has tiles; then the energies and
+ * lambda = H psi, then the adjoint levels in reverse.  The first run of each
+ * kind (with or without gradients) captures that launch sequence as a HIP
+ * graph; later runs replay it after uploading new parameters.
+ * stream: the HIP stream to run on, or NULL for a stream the batch creates
+ * and owns.  params_packed holds every instance's parameters back to back in
+ * instance order; energies gets count doubles; grads (may be NULL: then the
+ * adjoint levels are skipped) gets the gradients packed like params.  Runs
+ * synchronise the batch's stream. */
 qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs* const* obs, qs_dtype dt,
                           void* stream, qs_batch** out);
 qs_status qs_batch_run(qs_batch* b, const double* params_packed, double* energies, double* grads);

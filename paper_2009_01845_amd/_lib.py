@@ -27,7 +27,7 @@ class Callbacks(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("tile_bits", C.c_int32), ("fuse_k", C.c_int32), ("use_mfma", C.c_int32),
-                ("low_bits", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("low_bits", C.c_int32), ("lane_ops", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 _st = C.c_int32

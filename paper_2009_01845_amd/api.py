@@ -143,8 +143,8 @@ def circuit_add_rot(c, pauli: str, target: int, param_index: int, controls=()):
                                    _i32(controls)))
 
 
-def circuit_compile(c, tile_bits=0, fuse_k=0, use_mfma=-1, low_bits=0):
-    t = Tune(tile_bits, fuse_k, use_mfma, low_bits)
+def circuit_compile(c, tile_bits=0, fuse_k=0, use_mfma=-1, low_bits=0, lane_ops=0):
+    t = Tune(tile_bits, fuse_k, use_mfma, low_bits, int(lane_ops))
     check(lib().qs_circuit_compile(c, C.byref(t)))
 
 
@@ -541,12 +541,13 @@ class DensityCircuit(Circuit):
 
 
 # ---------------------------------------------------------------------- batch
-def batch_create(circs, observables, dt="c64"):
+def batch_create(circs, observables, dt="c64", stream=None):
     arr_c = (C.c_void_p * len(circs))(*[c.h.value for c in circs])
     arr_o = (C.c_void_p * len(observables))(*[o.h.value for o in observables])
     h = C.c_void_p()
     check(lib().qs_batch_create(len(circs), C.cast(arr_c, C.POINTER(C.c_void_p)),
-                                C.cast(arr_o, C.POINTER(C.c_void_p)), dtype_code(dt), None, C.byref(h)))
+                                C.cast(arr_o, C.POINTER(C.c_void_p)), dtype_code(dt),
+                                C.c_void_p(int(stream)) if stream is not None else None, C.byref(h)))
     return h
 
 
@@ -563,13 +564,15 @@ def batch_destroy(h):
 
 
 class Batch:
-    """Many circuits with their own parameters and diagonal observables in
-    one persistent launch (captured as a HIP graph on the first run)."""
+    """Many circuits with their own parameters and diagonal observables, run
+    level by level (one pass of every instance per launch) and captured as a
+    HIP graph on the first run.  stream: a HIP stream handle (int) or None
+    for a stream of the batch's own."""
 
-    def __init__(self, circuits, observables, dtype="c64"):
+    def __init__(self, circuits, observables, dtype="c64", stream=None):
         self.circuits, self.observables = list(circuits), list(observables)  # keep the handles alive
         self.nparams = sum(c.nparams for c in self.circuits)
-        self.h = batch_create(self.circuits, self.observables, dtype)
+        self.h = batch_create(self.circuits, self.observables, dtype, stream)
 
     def run(self, params_packed, want_grads: bool = True):
         return batch_run(self.h, params_packed, len(self.circuits), self.nparams, want_grads)

@@ -154,16 +154,30 @@ struct DevPlanBuf {
   bool has_scaled = false;
   DevPlan view;
   bool dbl = false;
-  std::vector<PassGeom> geoms;  // op0 filled in
+  std::vector<PassGeom> geoms;      // op0 filled in
+  std::vector<PassGeom> geoms_adj;  // the two-state (adjoint) form of each pass
   void load(const Plan& p, hipStream_t s) {
     std::vector<TileOp> all;
     geoms.clear();
+    geoms_adj.clear();
     for (const Pass& ps : p.passes) {
       PassGeom g = ps.geom;
       g.op0 = (int)all.size();
       g.nops = (int)ps.ops.size();
       all.insert(all.end(), ps.ops.begin(), ps.ops.end());
       geoms.push_back(g);
+    }
+    for (size_t i = 0; i < p.passes.size(); ++i) {
+      const Pass& ps = p.passes[i];
+      if (!ps.has_adj) {
+        geoms_adj.push_back(geoms[i]);
+        continue;
+      }
+      PassGeom g = ps.geom_adj;
+      g.op0 = (int)all.size();
+      g.nops = (int)ps.ops_adj.size();
+      all.insert(all.end(), ps.ops_adj.begin(), ps.ops_adj.end());
+      geoms_adj.push_back(g);
     }
     upload(ops, all, s);
     std::vector<double> m(p.matpool.size() * 2);
@@ -292,17 +306,26 @@ struct qs_batch {
   bool dbl = false;
   int nparams = 0;
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   std::vector<BatchInst> insts;
-  std::vector<PassGeom> geoms;
-  DBuf d_insts, d_order, d_geoms, d_ops, d_stages, d_matc, d_phases, d_phlist, d_dpool, d_btab, d_qtab, d_qang, d_ctab;
-  DBuf d_terms, d_slot_pidx, d_states, d_counter, d_params, d_gpart, d_energies, d_grads;
+  std::vector<PassGeom> geoms, geoms_adj;
+  // launch lists: forward levels, adjoint levels (item offset, count, ctrl),
+  // and the chunk items of initialisation and energy
+  struct Level {
+    int off, cnt;
+    bool ctrl;
+  };
+  std::vector<Level> fwd, adj;
+  int chunk_off = 0, nchunks = 0;
+  DBuf d_insts, d_geoms, d_geoms_adj, d_ops, d_stages, d_matc, d_phases, d_phlist, d_dpool, d_btab, d_qtab, d_qang, d_ctab;
+  DBuf d_terms, d_slot_pidx, d_op_inst, d_items, d_states, d_params, d_gpart, d_slot_sum, d_epart, d_energies,
+      d_grads;
   double* h_params = nullptr;
   double* h_energies = nullptr;
   double* h_grads = nullptr;
   BatchArgs args;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  bool captured = false;
+  hipGraph_t graph[2] = {nullptr, nullptr};  // [0] energies only, [1] energies and gradients
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -364,7 +387,8 @@ void run_passes(const DevPlanBuf& dp, const Plan& plan, bool dbl, void* psi, voi
       if (lam) hipck(launch_mfma_pass(dbl, lam, ps.geom, op.b, op.k, m, s), "mfma pass");
     } else {
       ProfScope pr(lam ? 7 : 0, s);
-      hipck(launch_tile_pass(dbl, psi, lam, dp.geoms[i], dp.view, params, scales, gpart, s), "tile pass");
+      hipck(launch_tile_pass(dbl, psi, lam, lam ? dp.geoms_adj[i] : dp.geoms[i], dp.view, params, scales, gpart, s),
+            "tile pass");
     }
   }
 }
@@ -728,7 +752,7 @@ qs_status qs_state_copy(qs_state* dst, const qs_state* src) {
     check_state(dst);
     check_state(src);
     if (dst->n != src->n || dst->dt != src->dt) fail(QS_E_STATE, "state shapes differ");
-    hipck(hipMemcpyAsync(dst->ptr, src->ptr, dst->bytes(), hipMemcpyDeviceToDevice, dst->stream), "copy");
+    hipck(launch_copy(dst->ptr, src->ptr, (int64_t)dst->bytes(), dst->stream), "copy");
   });
 }
 
@@ -920,10 +944,12 @@ qs_status qs_circuit_compile(qs_circuit* c, const qs_tune* opts) {
         fail(QS_E_INVALID, "tile_bits must be 0 or in [6, 13]");
       if (opts->fuse_k < 0 || opts->fuse_k > 5) fail(QS_E_INVALID, "fuse_k must be in [0, 5]");
       if (opts->low_bits < 0 || opts->low_bits > 8) fail(QS_E_INVALID, "low_bits must be in [0, 8]");
+      if (opts->lane_ops != 0 && opts->lane_ops != 1) fail(QS_E_INVALID, "lane_ops must be 0 or 1");
       o.tile_bits = opts->tile_bits;
       o.fuse_k = opts->fuse_k;
       o.use_mfma = opts->use_mfma;
       o.low_bits = opts->low_bits;
+      o.lane_ops = opts->lane_ops != 0;
     }
     c->hc.opts = o;
     // plan for complex64 now (host only); a complex128 run replans
@@ -1632,19 +1658,18 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
     auto b = std::make_unique<qs_batch>();
     b->count = count;
     b->dbl = dt == QS_C128;
-    (void)stream;
     std::vector<TileOp> ops;
     std::vector<StageRec> stages;
     std::vector<cd> mats;
     std::vector<PhaseRec> phases;
-    std::vector<int32_t> phlist;
+    std::vector<int32_t> phlist, op_inst;
     std::vector<double> dpool, btab, qang;
     std::vector<cd> qtab, ctab;
     std::vector<PauliTermDev> terms;
     std::vector<int32_t> slot_pidx;
-    std::vector<double> cost(count);
-    int64_t state_elems = 0;
-    int params = 0, slots = 0;
+    std::vector<std::vector<bool>> pass_ctrl(count);
+    int64_t state_elems = 0, gp_elems = 0;
+    int params = 0, slots = 0, chunks = 0;
     for (int i = 0; i < count; ++i) {
       qs_circuit* c = circs[i];
       const qs_obs* o = obs[i];
@@ -1654,7 +1679,7 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
       for (uint64_t f : o->flips)
         if (f != 0) fail(QS_E_UNSUPPORTED, "batch observables must be diagonal (I/Z strings)");
       TuneOpts opt = c->hc.opts;
-      opt.grid_bits = 0;
+      opt.grid_bits = kGridBits;  // one workgroup per tile: every tile-index bit is a grid bit
       opt.force_stage = true;
       Plan p = plan_circuit(c->hc, opt, b->dbl);
       BatchInst in;
@@ -1673,18 +1698,38 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
       in.ct_base = (int)ctab.size();
       for (const PhaseRec& r : p.phases)
         if (r.scale_idx >= 0) fail(QS_E_UNSUPPORTED, "batch circuits cannot hold run-time scaled phases");
-      int nops = 0;
+      int nops = 0, tbits = -1;
       for (const Pass& ps : p.passes) {
         if (ps.kind != PASS_TILE || ps.geom.kern != 2)
           fail(QS_E_UNSUPPORTED, "batch circuits must plan into register-blocked tiled passes (no SWAP or k>=3 gates)");
         PassGeom g = ps.geom;
+        if (tbits >= 0 && g.n - g.m != tbits) fail(QS_E_STATE, "internal: batch passes with different tile sizes");
+        tbits = g.n - g.m;
         g.op0 = nops;
         g.nops = (int)ps.ops.size();
         nops += g.nops;
         ops.insert(ops.end(), ps.ops.begin(), ps.ops.end());
+        op_inst.insert(op_inst.end(), ps.ops.size(), i);
         b->geoms.push_back(g);
+        pass_ctrl[i].push_back(g.ctrl != 0);
+      }
+      for (size_t k = 0; k < p.passes.size(); ++k) {  // the two-state form of each pass
+        const Pass& ps = p.passes[k];
+        if (!ps.has_adj) {
+          b->geoms_adj.push_back(b->geoms[in.pass0 + k]);
+          continue;
+        }
+        PassGeom g = ps.geom_adj;
+        g.op0 = nops;
+        g.nops = (int)ps.ops_adj.size();
+        nops += g.nops;
+        ops.insert(ops.end(), ps.ops_adj.begin(), ps.ops_adj.end());
+        op_inst.insert(op_inst.end(), ps.ops_adj.size(), i);
+        b->geoms_adj.push_back(g);
+        pass_ctrl[i][k] = pass_ctrl[i][k] || g.ctrl != 0;
       }
       in.nops = nops;
+      in.tbits = std::max(tbits, 0);
       stages.insert(stages.end(), p.stages.begin(), p.stages.end());
       mats.insert(mats.end(), p.matpool.begin(), p.matpool.end());
       phases.insert(phases.end(), p.phases.begin(), p.phases.end());
@@ -1700,6 +1745,8 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
       in.slot_base = slots;
       in.nslots = p.ngrad_slots;
       slots += p.ngrad_slots;
+      in.gp_off = gp_elems;
+      gp_elems += int64_t(p.ngrad_slots) * (4ll << in.tbits);
       std::vector<int32_t> sp(p.ngrad_slots, -1);
       for (const Pass& ps : p.passes)
         for (const TileOp& op : ps.ops)
@@ -1711,19 +1758,50 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
       in.state_off = state_elems;
       in.lam_off = state_elems + (1ll << in.n);
       state_elems += 2 * (1ll << in.n);
-      cost[i] = double(1ll << in.n) * (in.npass + 1);
+      in.e0 = chunks;
+      in.ne = (int)std::max<int64_t>(1, (1ll << in.n) >> kBatchChunkBits);
+      chunks += in.ne;
       b->insts.push_back(in);
     }
     b->nparams = params;
-    std::vector<int32_t> order(count);
+    // work items: the chunks, then forward level k = pass k of every instance
+    // that has it, then adjoint level k = pass npass-1-k; the largest
+    // instances first within a launch
+    std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    hipck(hipStreamCreate(&b->stream), "hipStreamCreate");
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->insts[x].n > b->insts[y].n; });
+    std::vector<BatchItem> items;
+    b->chunk_off = 0;
+    for (int i : order)
+      for (int cidx = 0; cidx < b->insts[i].ne; ++cidx) items.push_back(BatchItem{i, 0, cidx, 0});
+    b->nchunks = (int)items.size();
+    int maxp = 0;
+    for (const BatchInst& in : b->insts) maxp = std::max(maxp, in.npass);
+    for (int dir = 0; dir < 2; ++dir)
+      for (int k = 0; k < maxp; ++k) {
+        qs_batch::Level lv{(int)items.size(), 0, false};
+        for (int i : order) {
+          const BatchInst& in = b->insts[i];
+          if (k >= in.npass) continue;
+          const int pass = dir ? in.npass - 1 - k : k;
+          lv.ctrl = lv.ctrl || pass_ctrl[i][pass];
+          for (int t = 0; t < (1 << in.tbits); ++t) items.push_back(BatchItem{i, pass, t, 0});
+        }
+        lv.cnt = (int)items.size() - lv.off;
+        if (lv.cnt > 0) (dir ? b->adj : b->fwd).push_back(lv);
+      }
+    if (stream) {
+      b->stream = static_cast<hipStream_t>(stream);
+    } else {
+      hipck(hipStreamCreate(&b->stream), "hipStreamCreate");
+      b->own_stream = true;
+    }
     hipStream_t st = b->stream;
     upload(b->d_insts, b->insts, st);
-    upload(b->d_order, order, st);
     upload(b->d_geoms, b->geoms, st);
+    upload(b->d_geoms_adj, b->geoms_adj, st);
     upload(b->d_ops, ops, st);
+    upload(b->d_op_inst, op_inst, st);
     upload(b->d_stages, stages, st);
     upload(b->d_phases, phases, st);
     upload(b->d_phlist, phlist, st);
@@ -1732,6 +1810,7 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
     upload(b->d_qang, qang, st);
     upload(b->d_terms, terms, st);
     upload(b->d_slot_pidx, slot_pidx, st);
+    upload(b->d_items, items, st);
     {
       std::vector<double> m(mats.size() * 2), q(qtab.size() * 2);
       for (size_t i = 0; i < mats.size(); ++i) { m[2 * i] = mats[i].real(); m[2 * i + 1] = mats[i].imag(); }
@@ -1747,11 +1826,12 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
       }
     }
     const size_t esz = b->dbl ? 16 : 8;
-    check_mem(size_t(state_elems) * esz);
+    check_mem(size_t(state_elems) * esz + size_t(gp_elems) * 8);
     b->d_states.ensure(size_t(state_elems) * esz + 16);
-    b->d_counter.ensure(64);
     b->d_params.ensure(sizeof(double) * std::max(params, 1));
-    b->d_gpart.ensure(sizeof(double) * 4 * std::max(slots, 1));
+    b->d_gpart.ensure(sizeof(double) * std::max<int64_t>(gp_elems, 1));
+    b->d_slot_sum.ensure(sizeof(double) * std::max(slots, 1));
+    b->d_epart.ensure(sizeof(double) * std::max(chunks, 1));
     b->d_energies.ensure(sizeof(double) * count);
     b->d_grads.ensure(sizeof(double) * std::max(params, 1));
     hipck(hipHostMalloc((void**)&b->h_params, sizeof(double) * std::max(params, 1), hipHostMallocDefault),
@@ -1763,9 +1843,8 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
     BatchArgs& a = b->args;
     a.insts = b->d_insts.as<BatchInst>();
     a.count = count;
-    a.order = b->d_order.as<int32_t>();
-    a.counter = b->d_counter.as<int32_t>();
     a.geoms = b->d_geoms.as<PassGeom>();
+    a.geoms_adj = b->d_geoms_adj.as<PassGeom>();
     a.dp.ops = b->d_ops.as<TileOp>();
     a.dp.stages = b->d_stages.as<StageRec>();
     a.dp.matc = b->d_matc.p;
@@ -1776,37 +1855,49 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
     a.dp.qtab = b->d_qtab.p;
     a.dp.ctab = b->d_ctab.p;
     a.dp.qang = b->d_qang.as<double>();
+    a.op_inst = b->d_op_inst.as<int32_t>();
+    a.nops_total = (int)ops.size();
     a.states = b->d_states.p;
     a.params = b->d_params.as<double>();
     a.terms = b->d_terms.as<PauliTermDev>();
     a.slot_pidx = b->d_slot_pidx.as<int32_t>();
     a.gpart = b->d_gpart.as<double>();
+    a.slot_sum = b->d_slot_sum.as<double>();
+    a.epart = b->d_epart.as<double>();
     a.energies = b->d_energies.as<double>();
     a.grads = b->d_grads.as<double>();
-    int dev = 0, cus = 256;
-    hipck(hipGetDevice(&dev), "hipGetDevice");
-    hipck(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attribute");
-    a.grid = std::min(count, 2 * cus);
     *out = b.release();
   });
 }
 
 namespace {
-void batch_enqueue(qs_batch* b) {
+// One run of the batch on its stream: parameters in, rotation matrices,
+// |0..0>, the forward levels, energies and lambda, (the adjoint levels,)
+// energies and gradients out.  Only kernels and copies from pinned host
+// memory: the sequence is captured into a graph as it stands.
+void batch_enqueue(qs_batch* b, bool grads) {
   hipStream_t st = b->stream;
+  const BatchArgs& a = b->args;
+  const BatchItem* items = b->d_items.as<BatchItem>();
+  ProfScope pr(8, st);
   hipck(hipMemcpyAsync(b->d_params.p, b->h_params, sizeof(double) * std::max(b->nparams, 1),
                        hipMemcpyHostToDevice, st),
         "params");
-  hipck(launch_zero(reinterpret_cast<double*>(b->d_counter.p), 1, st), "zero");
-  {
-    ProfScope pr(8, st);
-    hipck(launch_batch(b->dbl, b->args, st), "batch kernel");
-  }
+  hipck(launch_batch_rot(b->dbl, a, st), "batch rotations");
+  hipck(launch_batch_init(b->dbl, a, items + b->chunk_off, b->nchunks, st), "batch init");
+  for (const qs_batch::Level& lv : b->fwd)
+    hipck(launch_batch_pass(b->dbl, a, items + lv.off, lv.cnt, 0, lv.ctrl, st), "batch forward level");
+  hipck(launch_batch_energy(b->dbl, a, items + b->chunk_off, b->nchunks, st), "batch energy");
+  if (grads)
+    for (const qs_batch::Level& lv : b->adj)
+      hipck(launch_batch_pass(b->dbl, a, items + lv.off, lv.cnt, 1, lv.ctrl, st), "batch adjoint level");
+  hipck(launch_batch_finish(a, grads, st), "batch finish");
   hipck(hipMemcpyAsync(b->h_energies, b->d_energies.p, sizeof(double) * b->count, hipMemcpyDeviceToHost, st),
         "energies");
-  hipck(hipMemcpyAsync(b->h_grads, b->d_grads.p, sizeof(double) * std::max(b->nparams, 1), hipMemcpyDeviceToHost,
-                       st),
-        "grads");
+  if (grads)
+    hipck(hipMemcpyAsync(b->h_grads, b->d_grads.p, sizeof(double) * std::max(b->nparams, 1),
+                         hipMemcpyDeviceToHost, st),
+          "grads");
 }
 }  // namespace
 
@@ -1815,27 +1906,28 @@ qs_status qs_batch_run(qs_batch* b, const double* params_packed, double* energie
     if (!b) fail(QS_E_INVALID, "null batch");
     if (b->nparams > 0 && !params_packed) fail(QS_E_INVALID, "null params");
     if (!energies) fail(QS_E_INVALID, "null energies");
+    const bool want = grads != nullptr;
+    hipck(hipStreamSynchronize(b->stream), "sync");  // the previous run's copies have landed
     if (b->nparams > 0) std::memcpy(b->h_params, params_packed, sizeof(double) * b->nparams);
-    if (!b->captured && !g_prof) {
+    if (!b->exec[want] && !g_prof) {
       hipStream_t st = b->stream;
       hipck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
       try {
-        batch_enqueue(b);
+        batch_enqueue(b, want);
       } catch (...) {
-        hipGraph_t gbad;
+        hipGraph_t gbad = nullptr;
         (void)hipStreamEndCapture(st, &gbad);
         if (gbad) (void)hipGraphDestroy(gbad);
         throw;
       }
-      hipck(hipStreamEndCapture(st, &b->graph), "end capture");
-      hipck(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
-      b->captured = true;
+      hipck(hipStreamEndCapture(st, &b->graph[want]), "end capture");
+      hipck(hipGraphInstantiate(&b->exec[want], b->graph[want], nullptr, nullptr, 0), "graph instantiate");
     }
-    if (b->captured && !g_prof) hipck(hipGraphLaunch(b->exec, b->stream), "graph launch");
-    else batch_enqueue(b);  // profiled runs launch eagerly so that their kernels are timed
+    if (b->exec[want] && !g_prof) hipck(hipGraphLaunch(b->exec[want], b->stream), "graph launch");
+    else batch_enqueue(b, want);  // profiled runs launch eagerly so that their kernels are timed
     hipck(hipStreamSynchronize(b->stream), "sync");
     std::memcpy(energies, b->h_energies, sizeof(double) * b->count);
-    if (grads && b->nparams > 0) std::memcpy(grads, b->h_grads, sizeof(double) * b->nparams);
+    if (want && b->nparams > 0) std::memcpy(grads, b->h_grads, sizeof(double) * b->nparams);
   });
 }
 
@@ -1843,12 +1935,14 @@ qs_status qs_batch_destroy(qs_batch* b) {
   return guard([&] {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int w = 0; w < 2; ++w) {
+      if (b->exec[w]) (void)hipGraphExecDestroy(b->exec[w]);
+      if (b->graph[w]) (void)hipGraphDestroy(b->graph[w]);
+    }
     if (b->h_params) (void)hipHostFree(b->h_params);
     if (b->h_energies) (void)hipHostFree(b->h_energies);
     if (b->h_grads) (void)hipHostFree(b->h_grads);
-    hipStream_t st = b->stream;
+    hipStream_t st = b->own_stream ? b->stream : nullptr;
     delete b;
     if (st) (void)hipStreamDestroy(st);
   });
@@ -1878,10 +1972,20 @@ uint64_t circuit_hash(const HostCircuit& hc) {
 }
 
 struct TuneChoice {
-  int tile_bits, fuse_k, use_mfma, low_bits;
+  int tile_bits, fuse_k, use_mfma, low_bits, lane_ops;
 };
 
-extern "C++" {  // a C++ helper: std::string result
+extern "C++" {  // C++ helpers: class-type results
+TuneOpts opts_of(const TuneChoice& t) {
+  TuneOpts o;
+  o.tile_bits = t.tile_bits;
+  o.fuse_k = t.fuse_k;
+  o.use_mfma = t.use_mfma;
+  o.low_bits = t.low_bits;
+  o.lane_ops = t.lane_ops != 0;
+  return o;
+}
+
 std::string tune_key(const qs_circuit* c, const qs_state* s) {
   int dev = 0;
   hipck(hipGetDevice(&dev), "hipGetDevice");
@@ -1906,10 +2010,11 @@ bool cache_lookup(const char* path, const std::string& key, TuneChoice* out) {
   while (std::fgets(line, sizeof line, f)) {
     const size_t kl = key.size();
     if (std::strncmp(line, key.c_str(), kl) != 0 || line[kl] != ' ') continue;
-    TuneChoice t;
-    if (std::sscanf(line + kl, " tile_bits=%d fuse_k=%d use_mfma=%d low_bits=%d", &t.tile_bits, &t.fuse_k,
-                    &t.use_mfma, &t.low_bits) == 4) {
-      *out = t;  // the last matching line wins
+    TuneChoice t{0, 0, -1, 0, 0};
+    const int got = std::sscanf(line + kl, " tile_bits=%d fuse_k=%d use_mfma=%d low_bits=%d lane_ops=%d", &t.tile_bits,
+                                &t.fuse_k, &t.use_mfma, &t.low_bits, &t.lane_ops);
+    if (got >= 4) {  // lines written before lane_ops existed read as lane_ops=0
+      *out = t;      // the last matching line wins
       found = true;
     }
   }
@@ -1921,18 +2026,13 @@ void cache_append(const char* path, const std::string& key, const TuneChoice& t,
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) fail(QS_E_INVALID, std::string("cannot open tuning cache ") + path);
-  std::fprintf(f, "%s tile_bits=%d fuse_k=%d use_mfma=%d low_bits=%d ms=%.4f\n", key.c_str(), t.tile_bits, t.fuse_k,
-               t.use_mfma, t.low_bits, ms);
+  std::fprintf(f, "%s tile_bits=%d fuse_k=%d use_mfma=%d low_bits=%d lane_ops=%d ms=%.4f\n", key.c_str(), t.tile_bits,
+               t.fuse_k, t.use_mfma, t.low_bits, t.lane_ops, ms);
   std::fclose(f);
 }
 
 void compile_with(qs_circuit* c, const TuneChoice& t, bool dbl, hipStream_t s) {
-  TuneOpts o;
-  o.tile_bits = t.tile_bits;
-  o.fuse_k = t.fuse_k;
-  o.use_mfma = t.use_mfma;
-  o.low_bits = t.low_bits;
-  c->hc.opts = o;
+  c->hc.opts = opts_of(t);
   c->planned = false;
   c->dev_ok = false;
   ensure_plan(c, dbl, s);
@@ -1963,7 +2063,11 @@ qs_status qs_autotune(qs_circuit* c, qs_state* s, const double* params, const ch
             "params upload");
       dpar = c->dparams.as<double>();
     }
-    std::vector<TuneChoice> cands = {{0, 0, -1, 0}, {0, 2, -1, 0}, {0, 3, 1, 0}, {0, 4, 1, 0}, {0, 5, 1, 0}};
+    // the default plan, lane ops, 13-bit tiles (complex64), low runs of 2^5
+    // amplitudes, then fusion widths with matrix cores
+    std::vector<TuneChoice> cands = {{0, 0, -1, 0, 0}, {0, 0, -1, 0, 1}, {0, 0, -1, 5, 0}, {0, 2, -1, 0, 0},
+                                     {0, 3, 1, 0, 0},  {0, 4, 1, 0, 0},  {0, 5, 1, 0, 0}};
+    if (!dbl) cands.push_back({13, 0, -1, 0, 0});
     DBuf ref;
     ref.ensure(s->bytes());
     double* part = scratch_doubles(s, kGridMax + 8);
@@ -1982,11 +2086,7 @@ qs_status qs_autotune(qs_circuit* c, qs_state* s, const double* params, const ch
     TuneChoice best = cands[0];
     for (size_t ci = 0; ci < cands.size(); ++ci) {
       const TuneChoice& t = cands[ci];
-      TuneOpts o;
-      o.tile_bits = t.tile_bits;
-      o.fuse_k = t.fuse_k;
-      o.use_mfma = t.use_mfma;
-      o.low_bits = t.low_bits;
+      const TuneOpts o = opts_of(t);
       Plan p;
       try {
         p = plan_circuit(c->hc, o, dbl);

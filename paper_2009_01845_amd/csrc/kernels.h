@@ -75,33 +75,58 @@ struct PauliTermTile {
 struct BatchInst {
   int32_t n, npass, pass0, nops;
   int32_t ops_base, st_base, mat_base, ph_base;
-  int32_t phl_base, dp_base, bt_base, qt_base, ct_base;
-  int32_t param_base, nparams, slot_base, nslots;
-  int32_t obs_off, obs_nterms, pad0, pad1;
-  int64_t state_off, lam_off;  // elements of the batch state buffer
+  int32_t phl_base, dp_base, bt_base, qt_base;
+  int32_t ct_base, param_base, nparams, slot_base;
+  int32_t nslots, obs_off, obs_nterms, tbits;  // tbits: log2 of the tiles of each pass
+  int32_t e0, ne, pad0, pad1;                  // energy / initialisation items [e0, e0 + ne)
+  int64_t state_off, lam_off;                  // elements of the batch state buffer
+  int64_t gp_off;                              // gradient partials: [slot][tile][wave] from here
 };
+
+// One workgroup's share of a batch launch: a tile of one pass of one
+// instance (pass launches), or a chunk of 2^kBatchChunkBits amplitudes of one
+// instance (initialisation and energy launches).
+struct BatchItem {
+  int32_t inst, pass, tile, pad;
+};
+constexpr int kBatchChunkBits = 12;
 
 struct BatchArgs {
   const BatchInst* insts = nullptr;
   int count = 0;
-  const int32_t* order = nullptr;  // instances, largest first
-  int32_t* counter = nullptr;      // work queue head (zeroed before the launch)
   const PassGeom* geoms = nullptr;
+  const PassGeom* geoms_adj = nullptr;  // the two-state form of each pass
   DevPlan dp;                      // concatenated pools; matc is written (rotations)
+  const int32_t* op_inst = nullptr;  // instance of every op of the concatenated op array
+  int nops_total = 0;
   void* states = nullptr;
   const double* params = nullptr;
   const PauliTermDev* terms = nullptr;  // diagonal observables, per instance
   const int32_t* slot_pidx = nullptr;
-  double* gpart = nullptr;         // 4 partials per gradient slot
+  double* gpart = nullptr;         // gradient partials (BatchInst::gp_off)
+  double* slot_sum = nullptr;      // per gradient slot, summed over tiles and waves
+  double* epart = nullptr;         // per energy item
   double* energies = nullptr;
   double* grads = nullptr;
-  int grid = 0;
 };
 
-// Persistent launch: workgroups take instances from the queue until it is
-// empty; each runs its instance's forward passes from |0..0>, the energy of
-// its diagonal observable, lambda = H psi, and the reverse adjoint sweep.
-hipError_t launch_batch(bool dbl, const BatchArgs& a, hipStream_t s);
+// Batched instances run level by level: every launch takes one pass of every
+// instance that has it, one workgroup per tile, so a large instance spreads
+// over as many workgroups as it has tiles.
+//   rot:    rotation matrices of every op from params
+//   init:   every instance's state to |0..0> (energy items)
+//   pass:   items[0..nitems) of one level; dir 0 forward, 1 adjoint (psi and
+//           lambda, gradient partials); ctrl selects the variant with
+//           in-tile controls
+//   energy: E = sum d(x) |psi(x)|^2 of each diagonal observable per item,
+//           lambda = d psi
+//   finish: energies and (with grads) the gradient of every parameter
+hipError_t launch_batch_rot(bool dbl, const BatchArgs& a, hipStream_t s);
+hipError_t launch_batch_init(bool dbl, const BatchArgs& a, const BatchItem* items, int nitems, hipStream_t s);
+hipError_t launch_batch_pass(bool dbl, const BatchArgs& a, const BatchItem* items, int nitems, int dir, bool ctrl,
+                             hipStream_t s);
+hipError_t launch_batch_energy(bool dbl, const BatchArgs& a, const BatchItem* items, int nitems, hipStream_t s);
+hipError_t launch_batch_finish(const BatchArgs& a, bool grads, hipStream_t s);
 
 // Fill the forward and inverse matrices of every rotation op from params.
 hipError_t launch_rot_mats(bool dbl, const DevPlan& dp, const double* params, hipStream_t s);
@@ -152,6 +177,8 @@ hipError_t launch_sample(bool dbl, const void* psi, int n, double* blocksums, do
                          int64_t shots, uint64_t seed, const double* uniforms, const int* pos, int m, int64_t* out,
                          hipStream_t s);
 // zero `count` doubles with a kernel (graph-capture safe)
+// dst <- src, bytes a multiple of 16 and both 16-byte aligned (streaming kernel)
+hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s);
 int sample_nblocks(int n);
 int sample_nchunks(int n);

@@ -548,6 +548,28 @@ __global__ void k_zero(double* p, int64_t count) {
     p[i] = 0.0;
 }
 
+// Streaming copy of nvec 16-byte vectors: every thread has kCopyUnroll
+// non-temporal loads in flight before its first store; consecutive threads
+// take consecutive vectors, so each wave moves whole 1 KiB runs.  Also the
+// measured streaming ceiling the pass kernels are compared with.
+constexpr int kCopyUnroll = 8;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(u32x4* __restrict__ dst, const u32x4* __restrict__ src, int64_t nvec) {
+  const int64_t chunk = int64_t(kThreads) * kCopyUnroll;
+  const int64_t nfull = nvec / chunk;
+  for (int64_t c = blockIdx.x; c < nfull; c += gridDim.x) {
+    const int64_t b = c * chunk + threadIdx.x;
+    u32x4 v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(src + b + u * kThreads);
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + b + u * kThreads);
+  }
+  // the ragged tail (fewer than kThreads * kCopyUnroll vectors), first workgroup only
+  if (blockIdx.x == 0)
+    for (int64_t i = nfull * chunk + threadIdx.x; i < nvec; i += kThreads) dst[i] = src[i];
+}
+
 template <typename R>
 __global__ void k_set_one(typename CT<R>::C* psi, uint64_t x) {
   psi[x] = mk<typename CT<R>::C>(1.0, 0.0);
@@ -1389,6 +1411,69 @@ __device__ __forceinline__ void op1d(C* v, C* w, const C* __restrict__ mp) {
   if (TWO) r1d<K>(w, a, d);
 }
 
+// ---- lane ops: a one-qubit op on the tile bit held by lane bit J (J < 4) of
+// the stage's thread-group index.  The partner amplitude of register element
+// e sits in the same element of lane (lane ^ 2^J), in the same row of 16
+// lanes, and is read with DPP moves: quad_perm for J = 0, 1; row_half_mirror
+// (lane ^ 7) then quad_perm (^ 3) for J = 2; row_ror:8 for J = 3.  Each lane
+// computes its own output: own * a + partner * c, with (a, c) = (m00, m01)
+// where its bit is 0 and (m11, m10) where it is 1.  Only one-state passes
+// hold lane ops: the planner stages the two-state (adjoint) form of a pass
+// without them.
+template <int J> __device__ __forceinline__ int lane_xor32(int v) {
+  if (J == 0) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  if (J == 1) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  if (J == 2) return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
+}
+template <int J> __device__ __forceinline__ float lane_xor(float x) {
+  return __int_as_float(lane_xor32<J>(__float_as_int(x)));
+}
+template <int J> __device__ __forceinline__ double lane_xor(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = lane_xor32<J>((int)(b & 0xffffffffll)), hi = lane_xor32<J>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// FORM 0: general complex matrix; 1: real; 2: diagonal; 3: [[a, i t], [i t, a]]
+template <int J, int FORM, typename C>
+__device__ __forceinline__ void rlane(C* v, const C* __restrict__ mp, int tid) {
+  const bool hi = (tid >> J) & 1;
+  const C a = hi ? mp[3] : mp[0];
+  const C c = hi ? mp[2] : mp[1];
+  if (FORM == 2) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) cmul_ip(v[e], a);
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    // keep one element's exchange in flight at a time (the empty asm is
+    // ordered against the previous element's): hoisting all sixteen would
+    // hold 32 more registers across the whole op dispatch
+    asm volatile("" : "+v"(v[e].x), "+v"(v[e].y));
+    const auto px = lane_xor<J>(v[e].x), py = lane_xor<J>(v[e].y);
+    auto x = v[e].x, y = v[e].y;
+    if (FORM == 1) {
+      x = a.x * x + c.x * px;
+      y = a.x * y + c.x * py;
+    } else if (FORM == 3) {  // a = (a, 0), c = (0, t)
+      x = a.x * x - c.y * py;
+      y = a.x * y + c.y * px;
+    } else {
+      const auto tx = -a.y * y + c.x * px - c.y * py;
+      const auto ty = a.y * x + c.x * py + c.y * px;
+      x = a.x * x + tx;
+      y = a.x * y + ty;
+    }
+    v[e].x = x;
+    v[e].y = y;
+  }
+}
+template <int J, int FORM, bool TWO, typename C>
+__device__ __forceinline__ void oplane(C* v, C* w, const C* __restrict__ mp, int tid) {
+  rlane<J, FORM>(v, mp, tid);
+  if (TWO) rlane<J, FORM>(w, mp, tid);
+}
 template <bool TWO, typename C>
 __device__ __forceinline__ void apply_signs(C* v, C* w, uint32_t S) {
 #pragma unroll
@@ -1527,16 +1612,14 @@ __device__ __forceinline__ double rgrad_any(const C* ps, const C* la, int k, uin
 // LDS scratch of a staged pass (besides the tile itself)
 struct PassSmem {
   uint64_t hoff[128];
-  double phA[kMaxPhasePerPass];
-  double phNu[kMaxPhasePerPass][kMaxTileBits];
   double phA0[kMaxPhasePerPass];
   double phNu0[kMaxPhasePerPass][kMaxTileBits];
   double phCk[kMaxPhasePerPass][kMaxKBits];
-  uint32_t phS[kMaxPhasePerPass];  // bit b: phNu[p][b] / pi odd; bit 31: phA[p] / pi odd
+  uint32_t phS[kMaxPhasePerPass];  // sign records: bit b set when the tile-bit-b angle / pi is odd, bit 31 for the constant
   int hb[kMaxTileBits];
   int kpos[kMaxKBits];
 };
-constexpr int kEnRow = kMaxTileBits + 1;  // exp(i phNu[p][b]) for tile bits b, exp(i phA[p]) at b = kMaxTileBits
+constexpr int kEnRow = kMaxTileBits + 1;  // exp(i angle) of tile bit b's coefficient, the constant's at b = kMaxTileBits
 
 // One staged pass over tiles t_first, t_first + t_step, ... < ntiles; the
 // tile-index bits above gbits are the "k bits" of the phase tables.  GUARD:
@@ -1566,8 +1649,6 @@ __device__ __forceinline__ void pass_body(
   C* t1 = reinterpret_cast<C*>(smem);
   C* t2 = TWO && !SEQ ? t1 + M : nullptr;
   uint64_t* hoff = sm.hoff;
-  auto& phA = sm.phA;
-  auto& phNu = sm.phNu;
   auto& phA0 = sm.phA0;
   auto& phNu0 = sm.phNu0;
   auto& phCk = sm.phCk;
@@ -1695,10 +1776,15 @@ __device__ __forceinline__ void pass_body(
       for (int half = 0; half < (TWO ? 2 : 1); ++half) {
         const C* src = half ? lam : psi;
         C* dst = half ? t2 : t1;
-        VT buf[NLD];  // issue every load of the tile before the first LDS write
+        // issue every load of the tile before the first LDS write; threads
+        // past a small tile load its first vector instead (every element of
+        // buf is assigned, so it stays in registers) and drop it
+        VT buf[NLD];
 #pragma unroll
-        for (int u = 0; u < NLD; ++u)
-          if (!GUARD || (u * kThreads + tid) * VW < M) buf[u] = *reinterpret_cast<const VT*>(src + gaddr(base, u));
+        for (int u = 0; u < NLD; ++u) {
+          const bool ok = !GUARD || (u * kThreads + tid) * VW < M;
+          buf[u] = *reinterpret_cast<const VT*>(src + (ok ? gaddr(base, u) : base));
+        }
 #pragma unroll
         for (int u = 0; u < NLD; ++u)
           if (!GUARD || (u * kThreads + tid) * VW < M)
@@ -1720,18 +1806,24 @@ __device__ __forceinline__ void pass_body(
           for (int j = 0; j < kMaxKBits; ++j)
             if ((kk >> j) & 1) s += kt[b * kMaxKBits + j];
           const double a = phNu0[p][b] + scl * s;
-          phNu[p][b] = a;
-          en[p * kEnRow + b] = expi<C>(a);
-          if (pi_parity(a)) atomicOr(&sm.phS[p], 1u << b);
+          // a sign record (every angle a multiple of pi: no complex factors,
+          // ctab_n = 0) needs only the parities, the others only the factors
+          if (rec.ctab_n == 0) {
+            if (pi_parity(a)) atomicOr(&sm.phS[p], 1u << b);
+          } else {
+            en[p * kEnRow + b] = expi<C>(a);
+          }
         } else if (b == 15) {
           double s = phA0[p];
 #pragma unroll
           for (int j = 0; j < kMaxKBits; ++j)
             if ((kk >> j) & 1) s += phCk[p][j];
           const double a = s + scl * kt[m * kMaxKBits + kk];
-          phA[p] = a;
-          en[p * kEnRow + kMaxTileBits] = expi<C>(a);
-          if (pi_parity(a)) atomicOr(&sm.phS[p], 1u << 31);
+          if (rec.ctab_n == 0) {
+            if (pi_parity(a)) atomicOr(&sm.phS[p], 1u << 31);
+          } else {
+            en[p * kEnRow + kMaxTileBits] = expi<C>(a);
+          }
         }
       }
       __syncthreads();
@@ -1903,7 +1995,10 @@ __device__ __forceinline__ void pass_body(
             // one flat switch over a uniform opcode with compile-time slots:
             // straight-line cases keep the register array in place
             int opc;
-            if (kind == OP_DENSE1 || kind == OP_ROT)
+            if ((kind == OP_DENSE1 || kind == OP_ROT) && (ops[o].flags & 32u))  // lane ops
+              opc = 40 + 4 * ((ops[o].flags & 16u) ? 2 : (ops[o].flags & 8u) ? 3 : (ops[o].flags & 1u) ? 1 : 0) +
+                    ops[o].b[0];
+            else if (kind == OP_DENSE1 || kind == OP_ROT)
               opc = ((ops[o].flags & 16u) ? 24 : (ops[o].flags & 8u) ? 28 : (ops[o].flags & 1u) ? 4 : 0) + ops[o].b[0];
             else if (kind == OP_DENSE2) {
               const int kh = ops[o].b[0], kl = ops[o].b[1];
@@ -1942,6 +2037,22 @@ __device__ __forceinline__ void pass_body(
               case 29: op1x<1, TWO>(v, w, m1); break;
               case 30: op1x<2, TWO>(v, w, m1); break;
               case 31: op1x<3, TWO>(v, w, m1); break;
+              case 40: if constexpr (!TWO) oplane<0, 0, TWO>(v, w, m1, tid); break;
+              case 41: if constexpr (!TWO) oplane<1, 0, TWO>(v, w, m1, tid); break;
+              case 42: if constexpr (!TWO) oplane<2, 0, TWO>(v, w, m1, tid); break;
+              case 43: if constexpr (!TWO) oplane<3, 0, TWO>(v, w, m1, tid); break;
+              case 44: if constexpr (!TWO) oplane<0, 1, TWO>(v, w, m1, tid); break;
+              case 45: if constexpr (!TWO) oplane<1, 1, TWO>(v, w, m1, tid); break;
+              case 46: if constexpr (!TWO) oplane<2, 1, TWO>(v, w, m1, tid); break;
+              case 47: if constexpr (!TWO) oplane<3, 1, TWO>(v, w, m1, tid); break;
+              case 48: if constexpr (!TWO) oplane<0, 2, TWO>(v, w, m1, tid); break;
+              case 49: if constexpr (!TWO) oplane<1, 2, TWO>(v, w, m1, tid); break;
+              case 50: if constexpr (!TWO) oplane<2, 2, TWO>(v, w, m1, tid); break;
+              case 51: if constexpr (!TWO) oplane<3, 2, TWO>(v, w, m1, tid); break;
+              case 52: if constexpr (!TWO) oplane<0, 3, TWO>(v, w, m1, tid); break;
+              case 53: if constexpr (!TWO) oplane<1, 3, TWO>(v, w, m1, tid); break;
+              case 54: if constexpr (!TWO) oplane<2, 3, TWO>(v, w, m1, tid); break;
+              case 55: if constexpr (!TWO) oplane<3, 3, TWO>(v, w, m1, tid); break;
               default: break;
             }
             continue;
@@ -1994,9 +2105,10 @@ __device__ __forceinline__ void pass_body(
       }
       VT buf[NLD];
 #pragma unroll
-      for (int u = 0; u < NLD; ++u)
-        if (!GUARD || (u * kThreads + tid) * VW < M)
-          buf[u] = *reinterpret_cast<const VT*>(src + swz<R>((u * kThreads + tid) * VW));
+      for (int u = 0; u < NLD; ++u) {
+        const bool ok = !GUARD || (u * kThreads + tid) * VW < M;
+        buf[u] = *reinterpret_cast<const VT*>(src + swz<R>(ok ? (u * kThreads + tid) * VW : 0));
+      }
 #pragma unroll
       for (int u = 0; u < NLD; ++u)
         if (!GUARD || (u * kThreads + tid) * VW < M) *reinterpret_cast<VT*>(dstg + gaddr(base, u)) = buf[u];
@@ -2189,83 +2301,109 @@ __device__ __forceinline__ void rot_fill(C* m, int pauli, double theta) {
   }
 }
 
-template <typename R, int NLD>
-__global__ __launch_bounds__(256) void k_batch(const BatchArgs a) {
+// ----------------------------------------------------------------------------
+// batched instances, one level (one pass of every instance that has it) per
+// launch; each workgroup takes one tile of one instance's pass
+// ----------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_rot(const BatchArgs a) {
+  using C = typename CT<R>::C;
+  const int o = blockIdx.x * kThreads + threadIdx.x;
+  if (o >= a.nops_total) return;
+  const TileOp op = a.dp.ops[o];
+  if (op.kind != OP_ROT || op.mat < 0) return;
+  const BatchInst& in = a.insts[a.op_inst[o]];
+  rot_fill(reinterpret_cast<C*>(a.dp.matc) + in.mat_base + op.mat, op.pauli,
+           op.sign * a.params[in.param_base + op.pidx]);
+}
+
+// psi = |0..0> over one chunk of one instance
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_init(const BatchArgs a, const BatchItem* __restrict__ items) {
+  using C = typename CT<R>::C;
+  const BatchItem it = items[blockIdx.x];
+  const BatchInst& in = a.insts[it.inst];
+  C* psi = reinterpret_cast<C*>(a.states) + in.state_off;
+  const int64_t N = 1ll << in.n;
+  const int64_t x0 = (int64_t)it.tile << kBatchChunkBits;
+  const int64_t x1 = x0 + (1ll << kBatchChunkBits) < N ? x0 + (1ll << kBatchChunkBits) : N;
+  for (int64_t x = x0 + threadIdx.x; x < x1; x += kThreads) psi[x] = mk<C>(x == 0 ? 1.0 : 0.0, 0.0);
+}
+
+template <typename R, bool TWO, int NLD, bool CTRL>
+__global__ __launch_bounds__(256) void k_batch_pass(const BatchArgs a, const BatchItem* __restrict__ items) {
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) char smem[];
   __shared__ PassSmem sm;
   __shared__ C en[kMaxPhasePerPass * kEnRow];
-  __shared__ double gacc[kMaxGradPerPass * (kThreads / 64)];
-  __shared__ int cur;
-  __shared__ double red[8];
-  const int tid = threadIdx.x;
-  C* matc = reinterpret_cast<C*>(a.dp.matc);
-  const C* qtab = reinterpret_cast<const C*>(a.dp.qtab);
-  const C* ctab = reinterpret_cast<const C*>(a.dp.ctab);
-  for (;;) {
-    if (tid == 0) cur = atomicAdd(a.counter, 1);
-    __syncthreads();
-    const int i = cur;
-    __syncthreads();
-    if (i >= a.count) break;  // every workgroup leaves once the queue is drained
-    const BatchInst in = a.insts[a.order[i]];
-    C* psi = reinterpret_cast<C*>(a.states) + in.state_off;
-    C* lam = reinterpret_cast<C*>(a.states) + in.lam_off;
-    const int64_t N = 1ll << in.n;
-    const double* par = a.params + in.param_base;
-    for (int o = tid; o < in.nops; o += kThreads) {
-      const TileOp op = a.dp.ops[in.ops_base + o];
-      if (op.kind == OP_ROT && op.mat >= 0) rot_fill(matc + in.mat_base + op.mat, op.pauli, op.sign * par[op.pidx]);
+  __shared__ double gacc[TWO ? kMaxGradPerPass * (kThreads / 64) : 1];
+  const BatchItem it = items[blockIdx.x];
+  const BatchInst& in = a.insts[it.inst];
+  C* psi = reinterpret_cast<C*>(a.states) + in.state_off;
+  C* lam = TWO ? reinterpret_cast<C*>(a.states) + in.lam_off : nullptr;
+  const PassGeom& g = (TWO ? a.geoms_adj : a.geoms)[in.pass0 + it.pass];
+  const int64_t nt = 1ll << in.tbits;
+  pass_body<R, TWO, NLD, true, CTRL>(
+      psi, lam, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
+      reinterpret_cast<const C*>(a.dp.matc) + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
+      a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, reinterpret_cast<const C*>(a.dp.qtab) + in.qt_base,
+      a.dp.qang + in.qt_base, nullptr, reinterpret_cast<const C*>(a.dp.ctab) + in.ct_base, a.gpart + in.gp_off,
+      4 * nt, it.tile * 4, it.tile, nt, nt, in.tbits, sm, smem, en, gacc);
+}
+
+// energy of the diagonal observable over one chunk, lambda = d psi there
+template <typename R>
+__global__ __launch_bounds__(256) void k_batch_energy(const BatchArgs a, const BatchItem* __restrict__ items) {
+  using C = typename CT<R>::C;
+  __shared__ double red[kThreads / 64];
+  const BatchItem it = items[blockIdx.x];
+  const BatchInst& in = a.insts[it.inst];
+  const C* psi = reinterpret_cast<const C*>(a.states) + in.state_off;
+  C* lam = reinterpret_cast<C*>(a.states) + in.lam_off;
+  const int64_t N = 1ll << in.n;
+  const int64_t x0 = (int64_t)it.tile << kBatchChunkBits;
+  const int64_t x1 = x0 + (1ll << kBatchChunkBits) < N ? x0 + (1ll << kBatchChunkBits) : N;
+  double acc = 0.0;
+  for (int64_t x = x0 + threadIdx.x; x < x1; x += kThreads) {
+    double d = 0.0;
+    for (int t = 0; t < in.obs_nterms; ++t) {
+      const PauliTermDev T = a.terms[in.obs_off + t];
+      d += (__popcll((uint64_t)x & T.zy) & 1) ? -T.coeff : T.coeff;
     }
-    for (int64_t x = tid; x < N; x += kThreads) psi[x] = mk<C>(x == 0 ? 1.0 : 0.0, 0.0);
-    double* gp = a.gpart + (int64_t)in.slot_base * 4;
-    for (int j = tid; j < in.nslots * 4; j += kThreads) gp[j] = 0.0;
-    __syncthreads();
-    for (int dir = 0; dir < 2; ++dir) {
-      if (dir == 1) {
-        // energy of the diagonal observable and lambda = H psi
-        double acc = 0.0;
-        for (int64_t x = tid; x < N; x += kThreads) {
-          double d = 0.0;
-          for (int t = 0; t < in.obs_nterms; ++t) {
-            const PauliTermDev T = a.terms[in.obs_off + t];
-            d += (__popcll((uint64_t)x & T.zy) & 1) ? -T.coeff : T.coeff;
-          }
-          const C v = psi[x];
-          acc += d * ((double)v.x * v.x + (double)v.y * v.y);
-          lam[x] = mk<C>(d * v.x, d * v.y);
-        }
-        const double e = block_sum(acc, red);
-        if (tid == 0) a.energies[a.order[i]] = e;
-        __syncthreads();
-      }
-      for (int k = 0; k < in.npass; ++k) {
-        const PassGeom& g = a.geoms[in.pass0 + (dir ? in.npass - 1 - k : k)];
-        const int64_t nt = 1ll << (g.n - g.m);
-        if (dir == 0)
-          pass_body<R, false, NLD, true, true>(psi, nullptr, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
-                                         matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
-                                         a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
-                                         a.dp.qang + in.qt_base, nullptr, ctab + in.ct_base, gp, 4, 0, 0, 1, nt,
-                                         0, sm, smem, en, gacc);
-        else
-          pass_body<R, true, NLD, true, true>(psi, lam, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
-                                        matc + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
-                                        a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, qtab + in.qt_base,
-                                        a.dp.qang + in.qt_base, nullptr, ctab + in.ct_base, gp, 4, 0, 0, 1, nt, 0,
-                                        sm, smem, en, gacc);
-      }
+    const C v = psi[x];
+    acc += d * ((double)v.x * v.x + (double)v.y * v.y);
+    lam[x] = mk<C>(d * v.x, d * v.y);
+  }
+  const double e = block_sum(acc, red);
+  if (threadIdx.x == 0) a.epart[in.e0 + it.tile] = e;  // the instance's chunks in index order
+}
+
+// one workgroup per instance: energy from its items in order; with grads,
+// every slot summed over its tiles and waves in order, then added into the
+// gradient of its parameter in slot order
+__global__ __launch_bounds__(256) void k_batch_finish(const BatchArgs a, int grads) {
+  const BatchInst& in = a.insts[blockIdx.x];
+  if (threadIdx.x == 0) {
+    double e = 0.0;
+    for (int i = 0; i < in.ne; ++i) e += a.epart[in.e0 + i];
+    a.energies[blockIdx.x] = e;
+  }
+  if (!grads) return;
+  const int cols = 4 << in.tbits;
+  for (int sl = threadIdx.x; sl < in.nslots; sl += kThreads) {
+    const double* p = a.gpart + in.gp_off + (int64_t)sl * cols;
+    double v = 0.0;
+    for (int c = 0; c < cols; ++c) v += p[c];
+    a.slot_sum[in.slot_base + sl] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* gr = a.grads + in.param_base;
+    for (int j = 0; j < in.nparams; ++j) gr[j] = 0.0;
+    for (int sl = 0; sl < in.nslots; ++sl) {
+      const int pidx = a.slot_pidx[in.slot_base + sl];
+      if (pidx >= 0) gr[pidx] += a.slot_sum[in.slot_base + sl];
     }
-    // gradient of every parameter, slots in order (deterministic)
-    if (tid == 0) {
-      double* gr = a.grads + in.param_base;
-      for (int j = 0; j < in.nparams; ++j) gr[j] = 0.0;
-      for (int sl = 0; sl < in.nslots; ++sl) {
-        const int pidx = a.slot_pidx[in.slot_base + sl];
-        if (pidx >= 0) gr[pidx] += gp[sl * 4] + gp[sl * 4 + 1] + gp[sl * 4 + 2] + gp[sl * 4 + 3];
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -2501,13 +2639,56 @@ hipError_t launch_mfma_pass(bool dbl, void* psi, const PassGeom& g, const int* t
   return mfma_launch_t<float, 5>(psi, g, ma, mat, s);
 }
 
-hipError_t launch_batch(bool dbl, const BatchArgs& a, hipStream_t s) {
-  if (a.count <= 0) return hipSuccess;
-  const size_t lds = (size_t(1) << 12) * (dbl ? 16 : 8) * 2;  // two tiles of up to 2^12 amplitudes
-  hipError_t e = dbl ? set_lds_fn((void*)k_batch<double, 16>, lds) : set_lds_fn((void*)k_batch<float, 8>, lds);
+hipError_t launch_batch_rot(bool dbl, const BatchArgs& a, hipStream_t s) {
+  if (a.nops_total <= 0) return hipSuccess;
+  const int grid = (a.nops_total + kThreads - 1) / kThreads;
+  if (dbl) hipLaunchKernelGGL((k_batch_rot<double>), dim3(grid), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((k_batch_rot<float>), dim3(grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init(bool dbl, const BatchArgs& a, const BatchItem* items, int nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (dbl) hipLaunchKernelGGL((k_batch_init<double>), dim3(nitems), dim3(kThreads), 0, s, a, items);
+  else hipLaunchKernelGGL((k_batch_init<float>), dim3(nitems), dim3(kThreads), 0, s, a, items);
+  return hipGetLastError();
+}
+
+template <typename R, bool TWO, int NLD, bool CTRL>
+hipError_t batch_pass_t(const BatchArgs& a, const BatchItem* items, int nitems, hipStream_t s) {
+  // tiles of up to 2^12 amplitudes; the two-state form keeps both in LDS
+  const size_t lds = (size_t(1) << 12) * sizeof(typename CT<R>::C) * (TWO ? 2 : 1);
+  hipError_t e = set_lds_fn((void*)k_batch_pass<R, TWO, NLD, CTRL>, lds);
   if (e != hipSuccess) return e;
-  if (dbl) hipLaunchKernelGGL((k_batch<double, 16>), dim3(a.grid), dim3(kThreads), lds, s, a);
-  else hipLaunchKernelGGL((k_batch<float, 8>), dim3(a.grid), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL((k_batch_pass<R, TWO, NLD, CTRL>), dim3(nitems), dim3(kThreads), lds, s, a, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pass(bool dbl, const BatchArgs& a, const BatchItem* items, int nitems, int dir, bool ctrl,
+                             hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (dbl) {
+    if (dir) return ctrl ? batch_pass_t<double, true, 16, true>(a, items, nitems, s)
+                         : batch_pass_t<double, true, 16, false>(a, items, nitems, s);
+    return ctrl ? batch_pass_t<double, false, 16, true>(a, items, nitems, s)
+                : batch_pass_t<double, false, 16, false>(a, items, nitems, s);
+  }
+  if (dir) return ctrl ? batch_pass_t<float, true, 8, true>(a, items, nitems, s)
+                       : batch_pass_t<float, true, 8, false>(a, items, nitems, s);
+  return ctrl ? batch_pass_t<float, false, 8, true>(a, items, nitems, s)
+              : batch_pass_t<float, false, 8, false>(a, items, nitems, s);
+}
+
+hipError_t launch_batch_energy(bool dbl, const BatchArgs& a, const BatchItem* items, int nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (dbl) hipLaunchKernelGGL((k_batch_energy<double>), dim3(nitems), dim3(kThreads), 0, s, a, items);
+  else hipLaunchKernelGGL((k_batch_energy<float>), dim3(nitems), dim3(kThreads), 0, s, a, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finish(const BatchArgs& a, bool grads, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_finish, dim3(a.count), dim3(kThreads), 0, s, a, grads ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -2531,6 +2712,18 @@ hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* t
   if (nld > 8) return hipErrorInvalidValue;
   return dbl ? perm_launch<double>(nld, psi, g, pa, nt, grid, lds, s)
              : perm_launch<float>(nld, psi, g, pa, nt, grid, lds, s);
+}
+
+hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s) {
+  if (bytes <= 0) return hipSuccess;
+  if (bytes % 16 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16)
+    return hipErrorInvalidValue;
+  const int64_t nvec = bytes / 16;
+  const int64_t chunks = nvec / (int64_t(kThreads) * kCopyUnroll);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, 4096));
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(kThreads), 0, s, static_cast<u32x4*>(dst),
+                     static_cast<const u32x4*>(src), nvec);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero(double* p, int64_t count, hipStream_t s) {

@@ -392,10 +392,14 @@ int ngrad_raw(const std::vector<RawOp>& raw) {
 bool has(const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); }
 
 // Register-blocked form of a pass (tiles of >= 2^12 amplitudes): split its op
-// list into stages whose dense targets all lie in kRegBits tile bits, and
-// rewrite the ops in register-slot terms.
-void stage_pass(Plan& plan, Pass& ps) {
-  PassGeom& g = ps.geom;
+// list into stages whose dense targets all lie in kRegBits tile bits (and,
+// with lanes, one-qubit ops on the lane bits), and rewrite the ops in
+// register-slot terms.
+void stage_ops(Plan& plan, PassGeom& g, std::vector<TileOp>& pops, bool lanes, bool* used_lanes) {
+  struct {
+    std::vector<TileOp>& ops;
+  } ps{pops};
+  if (used_lanes) *used_lanes = false;
   g.kern = 1;
   g.st0 = g.nst = g.ph0 = g.nph = 0;
   g.ctrl = 0;
@@ -500,6 +504,39 @@ void stage_pass(Plan& plan, Pass& ps) {
       if (best < 0) break;
       take(best);
     }
+    // lane ops: with the register set fixed (padded with the lowest free
+    // bits), uncontrolled one-qubit ops on the lowest non-register tile bits
+    // run in the same stage across lanes of a row (the group index's bits
+    // 0..3 are lane bits; a small tile has 2^(m-4) groups, so only bits whose
+    // partner group exists qualify)
+    {
+      for (int b = 0; (int)cur.rb.size() < kRegBits; ++b)
+        if (!has(cur.rb, b)) cur.rb.push_back(b);
+      uint32_t rmask = 0;
+      for (int b : cur.rb) rmask |= 1u << b;
+      const int nlane = lanes ? std::min(4, g.m - kRegBits) : 0;
+      uint32_t lmask = 0;
+      for (int b = 0, j = 0; b < g.m && j < nlane; ++b)
+        if (!((rmask >> b) & 1)) {
+          lmask |= 1u << b;
+          ++j;
+        }
+      for (bool grew = true; grew;) {
+        grew = false;
+        for (int i = 0; i < N; ++i) {
+          if (!ready(i)) continue;
+          const TileOp& op = ps.ops[i];
+          const bool fits = (tm[i] & ~rmask) == 0;
+          const bool lane = (op.kind == OP_DENSE1 || op.kind == OP_ROT) && op.cin == 0 && (tm[i] & ~lmask) == 0;
+          if (fits || lane) {
+            cur.ops.push_back(op);
+            done[i] = 1;
+            --left;
+            grew = true;
+          }
+        }
+      }
+    }
     if (cur.ops.empty()) throw std::runtime_error("planner: no op fits a register stage");
     sts.push_back(cur);
   }
@@ -532,8 +569,15 @@ void stage_pass(Plan& plan, Pass& ps) {
         else op.cin |= 1u << b;
       }
       const int dim = op.kind == OP_DENSE1 ? 2 : op.kind == OP_DENSE2 ? 4 : op.kind == OP_DENSEK ? (1 << op.k) : 0;
+      int lane_j = -1;  // lane op: index of its bit among the non-register tile bits
+      if ((op.kind == OP_DENSE1 || op.kind == OP_ROT) && slot_of[op.b[0]] < 0) {
+        lane_j = 0;
+        for (int b = 0; b < op.b[0]; ++b)
+          if (!((sr.rbmask >> b) & 1)) ++lane_j;
+        if (lane_j > 3 || cin != 0) throw std::runtime_error("planner: lane op outside the lane bits");
+      }
       if (op.kind == OP_DENSE1 || op.kind == OP_ROT) {
-        op.b[0] = slot_of[op.b[0]];
+        op.b[0] = lane_j >= 0 ? lane_j : slot_of[op.b[0]];
       } else if (op.kind == OP_DENSE2) {
         int s0 = slot_of[op.b[0]], s1 = slot_of[op.b[1]];
         if (s0 < s1) {  // make the higher slot the matrix MSB: swap the two index bits
@@ -696,6 +740,10 @@ void stage_pass(Plan& plan, Pass& ps) {
         if (diag) op.flags |= 16u;
         else if (xf) op.flags |= 8u;
       }
+      if (lane_j >= 0) {
+        op.flags |= 32u;
+        if (used_lanes) *used_lanes = true;
+      }
       if (op.cin != 0 || op.creg != 0) g.ctrl = 1;
       out.push_back(op);
     }
@@ -704,6 +752,40 @@ void stage_pass(Plan& plan, Pass& ps) {
   g.nst = (int)sts.size();
   ps.ops = out;
   g.kern = 2;
+}
+
+// Stage a pass; when its forward stages use lane ops, stage the same ops
+// again without them for the two-state kernel (its phase records are copies,
+// since a record's tables depend on the stage it sits in).
+void stage_pass(Plan& plan, Pass& ps) {
+  std::vector<TileOp> orig = ps.ops;
+  // staging may swap the two index bits of a two-qubit matrix (forward and
+  // inverse, 2 x 16 entries) in place: the second staging gets its own copy
+  // of the matrices as they are now
+  std::vector<int> mat2;
+  for (const TileOp& op : orig)
+    if (op.kind == OP_DENSE2) {
+      mat2.push_back((int)plan.matpool.size());
+      for (int i = 0; i < 32; ++i) plan.matpool.push_back(plan.matpool[op.mat + i]);
+    }
+  bool used = false;
+  stage_ops(plan, ps.geom, ps.ops, plan.lane_ops, &used);
+  ps.has_adj = false;
+  ps.ops_adj.clear();
+  if (ps.geom.kern != 2 || !used) return;  // (the copies stay unused)
+  size_t k2 = 0;
+  for (TileOp& op : orig) {
+    if (op.kind == OP_PHASE) {
+      plan.phases.push_back(plan.phases[op.aux]);
+      op.aux = (int)plan.phases.size() - 1;
+    } else if (op.kind == OP_DENSE2) {
+      op.mat = mat2[k2++];
+    }
+  }
+  ps.geom_adj = ps.geom;
+  stage_ops(plan, ps.geom_adj, orig, false, nullptr);
+  ps.ops_adj = std::move(orig);
+  ps.has_adj = true;
 }
 
 // Close an open pass: fix the tile bit set, convert ops to tile-local form,
@@ -957,6 +1039,7 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
   proto.ngates = (int)C.gates.size();
   proto.grid_bits = opts.grid_bits;
   proto.force_stage = opts.force_stage;
+  proto.lane_ops = opts.lane_ops;
   int m, L;
   default_tile(n, dbl, opts, &m, &L);
   const int Hmax = m - L;

@@ -33,6 +33,7 @@ struct TuneOpts {
   int low_bits = 0;
   int grid_bits = kGridBits;  // log2 of the workgroups walking a pass's tiles (0: one workgroup)
   bool force_stage = false;   // register-blocked stages also for tiles below 2^12
+  bool lane_ops = false;      // one-qubit ops on lane bits inside register stages
 };
 
 enum PassKind : int { PASS_TILE = 1, PASS_PHASE = 2, PASS_PERM = 3, PASS_MFMA = 4, PASS_DENSE = 5 };
@@ -42,6 +43,13 @@ struct Pass {
   PassGeom geom{};
   std::vector<TileOp> ops;
   std::vector<int> sigma;  // PASS_PERM: data at bit a moves to bit sigma[a] (an involution)
+  // staged passes whose forward stages hold lane ops: the same ops staged
+  // without lane ops, for the two-state (adjoint) kernel
+  bool has_adj = false;
+  PassGeom geom_adj{};
+  std::vector<TileOp> ops_adj;
+  const PassGeom& adj_geom() const { return has_adj ? geom_adj : geom; }
+  const std::vector<TileOp>& adj_ops() const { return has_adj ? ops_adj : ops; }
 };
 
 // Quadratic phase polynomial over global index bits.
@@ -83,6 +91,7 @@ struct Plan {
   int ngrad_slots = 0;           // ops carrying a trainable parameter
   int grid_bits = kGridBits;
   bool force_stage = false;
+  bool lane_ops = false;         // stages may hold lane ops (TuneOpts::lane_ops)
   int schedule = 0;              // high-bit choice that produced the plan: 0 index order,
                                  // 1 greedy lookahead, 2 one-step rollout
 };

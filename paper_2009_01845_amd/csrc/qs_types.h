@@ -41,7 +41,9 @@ struct TileOp {
   int32_t gslot;     // adjoint: gradient slot of this op (-1 if none)
   uint32_t creg;     // staged passes: control mask over register slots
   uint32_t flags;    // bit 0: the matrix is real; bit 1 (OP_PHASE): every term holds register slot b[0];
-                     // bit 2 (OP_PHASE): every coefficient is a multiple of pi (factors are +-1)
+                     // bit 2 (OP_PHASE): every coefficient is a multiple of pi (factors are +-1);
+                     // staged one-qubit ops: bit 3 [[a, it], [it, a]] form, bit 4 diagonal,
+                     // bit 5 lane op (b[0] = lane bit 0..3 of the thread-group index, not a slot)
 };
 
 constexpr int kRegBits = 4;            // register slots per thread in a staged pass

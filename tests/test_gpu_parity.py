@@ -68,7 +68,8 @@ def test_every_bit_position_1q_and_controlled(api, dt):
 
 # ---------------------------------------------------------------- circuits
 TILES = [dict(), dict(tile_bits=6, low_bits=1), dict(tile_bits=8, low_bits=3), dict(tile_bits=10, low_bits=4),
-         dict(tile_bits=12, low_bits=6), dict(tile_bits=13, low_bits=8)]
+         dict(tile_bits=12, low_bits=6), dict(tile_bits=13, low_bits=8), dict(lane_ops=1),
+         dict(tile_bits=13, low_bits=8, lane_ops=1)]
 
 
 @pytest.mark.parametrize("dt", DTS)
@@ -545,3 +546,27 @@ def test_bitwise_determinism(api):
         outs.append((st.download(), H.expectation(st), st.norm2()))
     assert np.array_equal(outs[0][0], outs[1][0])
     assert outs[0][1] == outs[1][1] and outs[0][2] == outs[1][2]
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_lane_op_plans_forward_and_adjoint(api, dt):
+    # register stages that also take one-qubit gates across lanes (DPP):
+    # the forward passes hold lane ops, the adjoint runs their lane-free form
+    n = 16
+    banner("lane ops", dt)
+    rng = np.random.default_rng(11)
+    params = rng.uniform(0, 2 * np.pi, (6, n))
+    spec = qsynth.ry_czring_layers(n, params)
+    terms = qsynth.zz_ring_plus_x(n)
+    flat = params.reshape(-1)
+    c = api.Circuit.from_spec(n, spec, lane_ops=1)
+    st = api.State(n, dt)
+    c.run(st, flat)
+    ref = ocirc.run(n, spec, None, flat)
+    assert maxabs(st.download(), ref) < TOL[dt]
+    H = api.Observable.pauli_sum(n, terms)
+    lam = api.State(n, dt)
+    E, g = api.adjoint(c.h, flat, H.h, st.h, lam.h, c.nparams)
+    E_ref, g_ref = ograd.adjoint(n, spec, flat, terms)
+    gtol = 1e-10 if dt == "c128" else 2e-4
+    assert abs(E - E_ref) < gtol and np.max(np.abs(g - g_ref)) < gtol
