@@ -402,8 +402,22 @@ def rows(only: str | None):
         torch.cuda.synchronize()
         t_eager = time.perf_counter() - t0
         gates = sum(cc.info()[0] for cc in circs)
+        # the batch tuner: per size class, the fastest candidate options
+        t0 = time.perf_counter()
+        b.autotune(bparams)
+        t_tune = time.perf_counter() - t0
+        b.run(bparams)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.run(bparams)
+        t_tuned = (time.perf_counter() - t0) / reps
+        table = {}
+        for i, (m, _, _, _) in enumerate(insts):
+            table.setdefault(str(m), b.choice(i))
         emit({"row": "M4", "workload": "512 variational instances, n ~ U{8..18}, depth ~ U{4..12}, complex64",
               "replay_ms": t_batch * 1e3, "replay_energies_only_ms": t_fwd * 1e3,
+              "replay_tuned_ms": t_tuned * 1e3, "tune_s": t_tune, "choice_by_n": table,
               "instances_per_s": len(insts) / t_batch, "forward_gates_per_s": gates / t_batch,
               "eager_instance_by_instance_ms": t_eager * 1e3, "speedup_vs_eager": t_eager / t_batch,
               "gates": gates, "params": int(off[-1])})

@@ -325,7 +325,8 @@ qs_status qs_adjoint(qs_circuit* c, const double* params, const qs_obs* H, qs_st
  * kind (with or without gradients) captures that launch sequence as a HIP
  * graph; later runs replay it after uploading new parameters.
  * stream: the HIP stream to run on, or NULL for a stream the batch creates
- * and owns.  params_packed holds every instance's parameters back to back in
+ * and owns.  The batch borrows the circuit and observable handles: they must
+ * outlive it.  params_packed holds every instance's parameters back to back in
  * instance order; energies gets count doubles; grads (may be NULL: then the
  * adjoint levels are skipped) gets the gradients packed like params.  Runs
  * synchronise the batch's stream. */
@@ -333,6 +334,20 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
                           void* stream, qs_batch** out);
 qs_status qs_batch_run(qs_batch* b, const double* params_packed, double* energies, double* grads);
 qs_status qs_batch_destroy(qs_batch* b);
+/* Tune a batch per size class (the instances with one qubit count): each
+ * candidate (the circuits' own options, lane ops, low runs of 2^5
+ * amplitudes, 10- and 11-bit tiles, two-qubit fusion) is run on a batch of
+ * that class alone, its launch sequence replayed as a graph and timed; the
+ * fastest whose energies and gradients agree with the first candidate's
+ * (1e-4 complex64, 1e-9 complex128) is kept, and the batch is rebuilt with
+ * each instance's choice.  params_packed as for qs_batch_run.  cache_path
+ * (may be NULL): a text file of earlier choices, one line per class key
+ * (qubit count, instance count, dtype, device, circuit hash), read first and
+ * appended to.  The batch's circuits and observables must still exist. */
+qs_status qs_batch_autotune(qs_batch* b, const double* params_packed, const char* cache_path);
+/* The options instance i of the batch runs with (after qs_batch_autotune, its
+ * class's choice; before, its circuit's own). */
+qs_status qs_batch_choice(const qs_batch* b, int32_t i, qs_tune* out);
 
 /* ------------------------------------------------------------------- tuner
  * Time the candidate plans (fusion width 0, 2..5, MFMA on/off) of c on

@@ -85,6 +85,8 @@ SIGNATURES = {
     "qs_batch_create": (_st, [_i32, _pp, _pp, _i32, _p, _pp]),
     "qs_batch_run": (_st, [_p, _f64p, _f64p, _f64p]),
     "qs_batch_destroy": (_st, [_p]),
+    "qs_batch_autotune": (_st, [_p, _f64p, C.c_char_p]),
+    "qs_batch_choice": (_st, [_p, _i32, C.POINTER(Tune)]),
     "qs_autotune": (_st, [_p, _p, _f64p, C.c_char_p]),
     "qs_profile_enable": (_st, [_i32]),
     "qs_profile_reset": (_st, []),

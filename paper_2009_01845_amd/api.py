@@ -577,6 +577,16 @@ class Batch:
     def run(self, params_packed, want_grads: bool = True):
         return batch_run(self.h, params_packed, len(self.circuits), self.nparams, want_grads)
 
+    def autotune(self, params_packed, cache_path: str | None = None):
+        keep, pp = _f64(params_packed if self.nparams else np.zeros(1))
+        check(lib().qs_batch_autotune(self.h, pp, cache_path.encode() if cache_path else None))
+
+    def choice(self, i: int) -> dict:
+        t = Tune()
+        check(lib().qs_batch_choice(self.h, i, C.byref(t)))
+        return {"tile_bits": t.tile_bits, "fuse_k": t.fuse_k, "use_mfma": t.use_mfma, "low_bits": t.low_bits,
+                "lane_ops": t.lane_ops}
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h is not None and h.value:

@@ -307,6 +307,9 @@ struct qs_batch {
   int nparams = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  std::vector<const qs_circuit*> circs;  // borrowed: they must outlive the batch
+  std::vector<const qs_obs*> obs;
+  std::vector<TuneOpts> opts;            // per instance (the circuit's, or the batch tuner's choice)
   std::vector<BatchInst> insts;
   std::vector<PassGeom> geoms, geoms_adj;
   // launch lists: forward levels, adjoint levels (item offset, count, ctrl),
@@ -1644,6 +1647,227 @@ qs_status qs_adjoint(qs_circuit* c, const double* params, const qs_obs* H, qs_st
 }
 
 // ------------------------------------------------------------------- batch
+namespace {
+// (Re)build a batch's plans, level lists and device tables from its circuits,
+// observables and per-instance options; any captured graphs are dropped.
+void batch_build(qs_batch* b) {
+  const int count = b->count;
+  for (int w = 0; w < 2; ++w) {
+    if (b->exec[w]) (void)hipGraphExecDestroy(b->exec[w]);
+    if (b->graph[w]) (void)hipGraphDestroy(b->graph[w]);
+    b->exec[w] = nullptr;
+    b->graph[w] = nullptr;
+  }
+  b->insts.clear();
+  b->geoms.clear();
+  b->geoms_adj.clear();
+  b->fwd.clear();
+  b->adj.clear();
+  hipck(hipStreamSynchronize(b->stream), "sync");
+  if (b->h_params) (void)hipHostFree(b->h_params);
+  if (b->h_energies) (void)hipHostFree(b->h_energies);
+  if (b->h_grads) (void)hipHostFree(b->h_grads);
+  b->h_params = b->h_energies = b->h_grads = nullptr;
+  std::vector<TileOp> ops;
+  std::vector<StageRec> stages;
+  std::vector<cd> mats;
+  std::vector<PhaseRec> phases;
+  std::vector<int32_t> phlist, op_inst;
+  std::vector<double> dpool, btab, qang;
+  std::vector<cd> qtab, ctab;
+  std::vector<PauliTermDev> terms;
+  std::vector<int32_t> slot_pidx;
+  std::vector<std::vector<bool>> pass_ctrl(count);
+  int64_t state_elems = 0, gp_elems = 0;
+  int params = 0, slots = 0, chunks = 0;
+  for (int i = 0; i < count; ++i) {
+    const qs_circuit* c = b->circs[i];
+    const qs_obs* o = b->obs[i];
+    TuneOpts opt = b->opts[i];
+    opt.grid_bits = kGridBits;  // one workgroup per tile: every tile-index bit is a grid bit
+    opt.force_stage = true;
+    Plan p = plan_circuit(c->hc, opt, b->dbl);
+    BatchInst in;
+    std::memset(&in, 0, sizeof(in));
+    in.n = c->hc.n;
+    in.npass = (int)p.passes.size();
+    in.pass0 = (int)b->geoms.size();
+    in.ops_base = (int)ops.size();
+    in.st_base = (int)stages.size();
+    in.mat_base = (int)mats.size();
+    in.ph_base = (int)phases.size();
+    in.phl_base = (int)phlist.size();
+    in.dp_base = (int)dpool.size();
+    in.bt_base = (int)btab.size();
+    in.qt_base = (int)qtab.size();
+    in.ct_base = (int)ctab.size();
+    for (const PhaseRec& r : p.phases)
+      if (r.scale_idx >= 0) fail(QS_E_UNSUPPORTED, "batch circuits cannot hold run-time scaled phases");
+    int nops = 0, tbits = -1;
+    for (const Pass& ps : p.passes) {
+      if (ps.kind != PASS_TILE || ps.geom.kern != 2)
+        fail(QS_E_UNSUPPORTED, "batch circuits must plan into register-blocked tiled passes (no SWAP or k>=3 gates)");
+      PassGeom g = ps.geom;
+      if (tbits >= 0 && g.n - g.m != tbits) fail(QS_E_STATE, "internal: batch passes with different tile sizes");
+      tbits = g.n - g.m;
+      g.op0 = nops;
+      g.nops = (int)ps.ops.size();
+      nops += g.nops;
+      ops.insert(ops.end(), ps.ops.begin(), ps.ops.end());
+      op_inst.insert(op_inst.end(), ps.ops.size(), i);
+      b->geoms.push_back(g);
+      pass_ctrl[i].push_back(g.ctrl != 0);
+    }
+    for (size_t k = 0; k < p.passes.size(); ++k) {  // the two-state form of each pass
+      const Pass& ps = p.passes[k];
+      if (!ps.has_adj) {
+        b->geoms_adj.push_back(b->geoms[in.pass0 + k]);
+        continue;
+      }
+      PassGeom g = ps.geom_adj;
+      g.op0 = nops;
+      g.nops = (int)ps.ops_adj.size();
+      nops += g.nops;
+      ops.insert(ops.end(), ps.ops_adj.begin(), ps.ops_adj.end());
+      op_inst.insert(op_inst.end(), ps.ops_adj.size(), i);
+      b->geoms_adj.push_back(g);
+      pass_ctrl[i][k] = pass_ctrl[i][k] || g.ctrl != 0;
+    }
+    in.nops = nops;
+    in.tbits = std::max(tbits, 0);
+    stages.insert(stages.end(), p.stages.begin(), p.stages.end());
+    mats.insert(mats.end(), p.matpool.begin(), p.matpool.end());
+    phases.insert(phases.end(), p.phases.begin(), p.phases.end());
+    phlist.insert(phlist.end(), p.phlist.begin(), p.phlist.end());
+    dpool.insert(dpool.end(), p.dpool.begin(), p.dpool.end());
+    btab.insert(btab.end(), p.btab.begin(), p.btab.end());
+    qtab.insert(qtab.end(), p.qtab.begin(), p.qtab.end());
+    qang.insert(qang.end(), p.qang.begin(), p.qang.end());
+    ctab.insert(ctab.end(), p.ctab.begin(), p.ctab.end());
+    in.param_base = params;
+    in.nparams = c->hc.nparams;
+    params += c->hc.nparams;
+    in.slot_base = slots;
+    in.nslots = p.ngrad_slots;
+    slots += p.ngrad_slots;
+    in.gp_off = gp_elems;
+    gp_elems += int64_t(p.ngrad_slots) * (4ll << in.tbits);
+    std::vector<int32_t> sp(p.ngrad_slots, -1);
+    for (const Pass& ps : p.passes)
+      for (const TileOp& op : ps.ops)
+        if (op.kind == OP_ROT && op.gslot >= 0) sp[op.gslot] = op.pidx;
+    slot_pidx.insert(slot_pidx.end(), sp.begin(), sp.end());
+    in.obs_off = (int)terms.size();
+    in.obs_nterms = (int)o->terms.size();
+    terms.insert(terms.end(), o->terms.begin(), o->terms.end());
+    in.state_off = state_elems;
+    in.lam_off = state_elems + (1ll << in.n);
+    state_elems += 2 * (1ll << in.n);
+    in.e0 = chunks;
+    in.ne = (int)std::max<int64_t>(1, (1ll << in.n) >> kBatchChunkBits);
+    chunks += in.ne;
+    b->insts.push_back(in);
+  }
+  b->nparams = params;
+  // work items: the chunks, then forward level k = pass k of every instance
+  // that has it, then adjoint level k = pass npass-1-k; the largest
+  // instances first within a launch
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->insts[x].n > b->insts[y].n; });
+  std::vector<BatchItem> items;
+  b->chunk_off = 0;
+  for (int i : order)
+    for (int cidx = 0; cidx < b->insts[i].ne; ++cidx) items.push_back(BatchItem{i, 0, cidx, 0});
+  b->nchunks = (int)items.size();
+  int maxp = 0;
+  for (const BatchInst& in : b->insts) maxp = std::max(maxp, in.npass);
+  for (int dir = 0; dir < 2; ++dir)
+    for (int k = 0; k < maxp; ++k) {
+      qs_batch::Level lv{(int)items.size(), 0, false};
+      for (int i : order) {
+        const BatchInst& in = b->insts[i];
+        if (k >= in.npass) continue;
+        const int pass = dir ? in.npass - 1 - k : k;
+        lv.ctrl = lv.ctrl || pass_ctrl[i][pass];
+        for (int t = 0; t < (1 << in.tbits); ++t) items.push_back(BatchItem{i, pass, t, 0});
+      }
+      lv.cnt = (int)items.size() - lv.off;
+      if (lv.cnt > 0) (dir ? b->adj : b->fwd).push_back(lv);
+    }
+  hipStream_t st = b->stream;
+  upload(b->d_insts, b->insts, st);
+  upload(b->d_geoms, b->geoms, st);
+  upload(b->d_geoms_adj, b->geoms_adj, st);
+  upload(b->d_ops, ops, st);
+  upload(b->d_op_inst, op_inst, st);
+  upload(b->d_stages, stages, st);
+  upload(b->d_phases, phases, st);
+  upload(b->d_phlist, phlist, st);
+  upload(b->d_dpool, dpool, st);
+  upload(b->d_btab, btab, st);
+  upload(b->d_qang, qang, st);
+  upload(b->d_terms, terms, st);
+  upload(b->d_slot_pidx, slot_pidx, st);
+  upload(b->d_items, items, st);
+  {
+    std::vector<double> m(mats.size() * 2), q(qtab.size() * 2);
+    for (size_t i = 0; i < mats.size(); ++i) { m[2 * i] = mats[i].real(); m[2 * i + 1] = mats[i].imag(); }
+    for (size_t i = 0; i < qtab.size(); ++i) { q[2 * i] = qtab[i].real(); q[2 * i + 1] = qtab[i].imag(); }
+    if (b->dbl) {
+      upload(b->d_matc, m, st);
+      upload(b->d_qtab, q, st);
+      upload_complex<double>(b->d_ctab, ctab, true, st);
+    } else {
+      upload(b->d_matc, std::vector<float>(m.begin(), m.end()), st);
+      upload(b->d_qtab, std::vector<float>(q.begin(), q.end()), st);
+      upload_complex<float>(b->d_ctab, ctab, false, st);
+    }
+  }
+  const size_t esz = b->dbl ? 16 : 8;
+  check_mem(size_t(state_elems) * esz + size_t(gp_elems) * 8);
+  b->d_states.ensure(size_t(state_elems) * esz + 16);
+  b->d_params.ensure(sizeof(double) * std::max(params, 1));
+  b->d_gpart.ensure(sizeof(double) * std::max<int64_t>(gp_elems, 1));
+  b->d_slot_sum.ensure(sizeof(double) * std::max(slots, 1));
+  b->d_epart.ensure(sizeof(double) * std::max(chunks, 1));
+  b->d_energies.ensure(sizeof(double) * count);
+  b->d_grads.ensure(sizeof(double) * std::max(params, 1));
+  hipck(hipHostMalloc((void**)&b->h_params, sizeof(double) * std::max(params, 1), hipHostMallocDefault),
+        "hipHostMalloc");
+  hipck(hipHostMalloc((void**)&b->h_energies, sizeof(double) * count, hipHostMallocDefault), "hipHostMalloc");
+  hipck(hipHostMalloc((void**)&b->h_grads, sizeof(double) * std::max(params, 1), hipHostMallocDefault),
+        "hipHostMalloc");
+  hipck(hipStreamSynchronize(st), "sync");
+  BatchArgs& a = b->args;
+  a.insts = b->d_insts.as<BatchInst>();
+  a.count = count;
+  a.geoms = b->d_geoms.as<PassGeom>();
+  a.geoms_adj = b->d_geoms_adj.as<PassGeom>();
+  a.dp.ops = b->d_ops.as<TileOp>();
+  a.dp.stages = b->d_stages.as<StageRec>();
+  a.dp.matc = b->d_matc.p;
+  a.dp.phases = b->d_phases.as<PhaseRec>();
+  a.dp.phlist = b->d_phlist.as<int32_t>();
+  a.dp.dpool = b->d_dpool.as<double>();
+  a.dp.btab = b->d_btab.as<double>();
+  a.dp.qtab = b->d_qtab.p;
+  a.dp.ctab = b->d_ctab.p;
+  a.dp.qang = b->d_qang.as<double>();
+  a.op_inst = b->d_op_inst.as<int32_t>();
+  a.nops_total = (int)ops.size();
+  a.states = b->d_states.p;
+  a.params = b->d_params.as<double>();
+  a.terms = b->d_terms.as<PauliTermDev>();
+  a.slot_pidx = b->d_slot_pidx.as<int32_t>();
+  a.gpart = b->d_gpart.as<double>();
+  a.slot_sum = b->d_slot_sum.as<double>();
+  a.epart = b->d_epart.as<double>();
+  a.energies = b->d_energies.as<double>();
+  a.grads = b->d_grads.as<double>();
+}
+}  // namespace
+
 qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs* const* obs, qs_dtype dt,
                           void* stream, qs_batch** out) {
   return guard([&] {
@@ -1652,220 +1876,28 @@ qs_status qs_batch_create(int32_t count, qs_circuit* const* circs, const qs_obs*
     if (count < 1) fail(QS_E_INVALID, "count must be >= 1");
     if (!circs || !obs) fail(QS_E_INVALID, "null circuits or observables");
     check_dtype(dt);
-    for (int i = 0; i < count; ++i)
-      if (circs[i] && circs[i]->dens) fail(QS_E_UNSUPPORTED, "batches take state-vector circuits only");
+    for (int i = 0; i < count; ++i) {
+      if (!circs[i] || !obs[i]) fail(QS_E_INVALID, "null circuit or observable in batch");
+      if (circs[i]->dens) fail(QS_E_UNSUPPORTED, "batches take state-vector circuits only");
+      if (obs[i]->n != circs[i]->hc.n) fail(QS_E_STATE, "observable and circuit sizes differ");
+      if (circs[i]->hc.n > 24) fail(QS_E_INVALID, "batch instances are limited to 24 qubits");
+      for (uint64_t f : obs[i]->flips)
+        if (f != 0) fail(QS_E_UNSUPPORTED, "batch observables must be diagonal (I/Z strings)");
+    }
     check_device();
     auto b = std::make_unique<qs_batch>();
     b->count = count;
     b->dbl = dt == QS_C128;
-    std::vector<TileOp> ops;
-    std::vector<StageRec> stages;
-    std::vector<cd> mats;
-    std::vector<PhaseRec> phases;
-    std::vector<int32_t> phlist, op_inst;
-    std::vector<double> dpool, btab, qang;
-    std::vector<cd> qtab, ctab;
-    std::vector<PauliTermDev> terms;
-    std::vector<int32_t> slot_pidx;
-    std::vector<std::vector<bool>> pass_ctrl(count);
-    int64_t state_elems = 0, gp_elems = 0;
-    int params = 0, slots = 0, chunks = 0;
-    for (int i = 0; i < count; ++i) {
-      qs_circuit* c = circs[i];
-      const qs_obs* o = obs[i];
-      if (!c || !o) fail(QS_E_INVALID, "null circuit or observable in batch");
-      if (o->n != c->hc.n) fail(QS_E_STATE, "observable and circuit sizes differ");
-      if (c->hc.n > 24) fail(QS_E_INVALID, "batch instances are limited to 24 qubits");
-      for (uint64_t f : o->flips)
-        if (f != 0) fail(QS_E_UNSUPPORTED, "batch observables must be diagonal (I/Z strings)");
-      TuneOpts opt = c->hc.opts;
-      opt.grid_bits = kGridBits;  // one workgroup per tile: every tile-index bit is a grid bit
-      opt.force_stage = true;
-      Plan p = plan_circuit(c->hc, opt, b->dbl);
-      BatchInst in;
-      std::memset(&in, 0, sizeof(in));
-      in.n = c->hc.n;
-      in.npass = (int)p.passes.size();
-      in.pass0 = (int)b->geoms.size();
-      in.ops_base = (int)ops.size();
-      in.st_base = (int)stages.size();
-      in.mat_base = (int)mats.size();
-      in.ph_base = (int)phases.size();
-      in.phl_base = (int)phlist.size();
-      in.dp_base = (int)dpool.size();
-      in.bt_base = (int)btab.size();
-      in.qt_base = (int)qtab.size();
-      in.ct_base = (int)ctab.size();
-      for (const PhaseRec& r : p.phases)
-        if (r.scale_idx >= 0) fail(QS_E_UNSUPPORTED, "batch circuits cannot hold run-time scaled phases");
-      int nops = 0, tbits = -1;
-      for (const Pass& ps : p.passes) {
-        if (ps.kind != PASS_TILE || ps.geom.kern != 2)
-          fail(QS_E_UNSUPPORTED, "batch circuits must plan into register-blocked tiled passes (no SWAP or k>=3 gates)");
-        PassGeom g = ps.geom;
-        if (tbits >= 0 && g.n - g.m != tbits) fail(QS_E_STATE, "internal: batch passes with different tile sizes");
-        tbits = g.n - g.m;
-        g.op0 = nops;
-        g.nops = (int)ps.ops.size();
-        nops += g.nops;
-        ops.insert(ops.end(), ps.ops.begin(), ps.ops.end());
-        op_inst.insert(op_inst.end(), ps.ops.size(), i);
-        b->geoms.push_back(g);
-        pass_ctrl[i].push_back(g.ctrl != 0);
-      }
-      for (size_t k = 0; k < p.passes.size(); ++k) {  // the two-state form of each pass
-        const Pass& ps = p.passes[k];
-        if (!ps.has_adj) {
-          b->geoms_adj.push_back(b->geoms[in.pass0 + k]);
-          continue;
-        }
-        PassGeom g = ps.geom_adj;
-        g.op0 = nops;
-        g.nops = (int)ps.ops_adj.size();
-        nops += g.nops;
-        ops.insert(ops.end(), ps.ops_adj.begin(), ps.ops_adj.end());
-        op_inst.insert(op_inst.end(), ps.ops_adj.size(), i);
-        b->geoms_adj.push_back(g);
-        pass_ctrl[i][k] = pass_ctrl[i][k] || g.ctrl != 0;
-      }
-      in.nops = nops;
-      in.tbits = std::max(tbits, 0);
-      stages.insert(stages.end(), p.stages.begin(), p.stages.end());
-      mats.insert(mats.end(), p.matpool.begin(), p.matpool.end());
-      phases.insert(phases.end(), p.phases.begin(), p.phases.end());
-      phlist.insert(phlist.end(), p.phlist.begin(), p.phlist.end());
-      dpool.insert(dpool.end(), p.dpool.begin(), p.dpool.end());
-      btab.insert(btab.end(), p.btab.begin(), p.btab.end());
-      qtab.insert(qtab.end(), p.qtab.begin(), p.qtab.end());
-      qang.insert(qang.end(), p.qang.begin(), p.qang.end());
-      ctab.insert(ctab.end(), p.ctab.begin(), p.ctab.end());
-      in.param_base = params;
-      in.nparams = c->hc.nparams;
-      params += c->hc.nparams;
-      in.slot_base = slots;
-      in.nslots = p.ngrad_slots;
-      slots += p.ngrad_slots;
-      in.gp_off = gp_elems;
-      gp_elems += int64_t(p.ngrad_slots) * (4ll << in.tbits);
-      std::vector<int32_t> sp(p.ngrad_slots, -1);
-      for (const Pass& ps : p.passes)
-        for (const TileOp& op : ps.ops)
-          if (op.kind == OP_ROT && op.gslot >= 0) sp[op.gslot] = op.pidx;
-      slot_pidx.insert(slot_pidx.end(), sp.begin(), sp.end());
-      in.obs_off = (int)terms.size();
-      in.obs_nterms = (int)o->terms.size();
-      terms.insert(terms.end(), o->terms.begin(), o->terms.end());
-      in.state_off = state_elems;
-      in.lam_off = state_elems + (1ll << in.n);
-      state_elems += 2 * (1ll << in.n);
-      in.e0 = chunks;
-      in.ne = (int)std::max<int64_t>(1, (1ll << in.n) >> kBatchChunkBits);
-      chunks += in.ne;
-      b->insts.push_back(in);
-    }
-    b->nparams = params;
-    // work items: the chunks, then forward level k = pass k of every instance
-    // that has it, then adjoint level k = pass npass-1-k; the largest
-    // instances first within a launch
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->insts[x].n > b->insts[y].n; });
-    std::vector<BatchItem> items;
-    b->chunk_off = 0;
-    for (int i : order)
-      for (int cidx = 0; cidx < b->insts[i].ne; ++cidx) items.push_back(BatchItem{i, 0, cidx, 0});
-    b->nchunks = (int)items.size();
-    int maxp = 0;
-    for (const BatchInst& in : b->insts) maxp = std::max(maxp, in.npass);
-    for (int dir = 0; dir < 2; ++dir)
-      for (int k = 0; k < maxp; ++k) {
-        qs_batch::Level lv{(int)items.size(), 0, false};
-        for (int i : order) {
-          const BatchInst& in = b->insts[i];
-          if (k >= in.npass) continue;
-          const int pass = dir ? in.npass - 1 - k : k;
-          lv.ctrl = lv.ctrl || pass_ctrl[i][pass];
-          for (int t = 0; t < (1 << in.tbits); ++t) items.push_back(BatchItem{i, pass, t, 0});
-        }
-        lv.cnt = (int)items.size() - lv.off;
-        if (lv.cnt > 0) (dir ? b->adj : b->fwd).push_back(lv);
-      }
+    b->circs.assign(circs, circs + count);
+    b->obs.assign(obs, obs + count);
+    for (int i = 0; i < count; ++i) b->opts.push_back(circs[i]->hc.opts);
     if (stream) {
       b->stream = static_cast<hipStream_t>(stream);
     } else {
       hipck(hipStreamCreate(&b->stream), "hipStreamCreate");
       b->own_stream = true;
     }
-    hipStream_t st = b->stream;
-    upload(b->d_insts, b->insts, st);
-    upload(b->d_geoms, b->geoms, st);
-    upload(b->d_geoms_adj, b->geoms_adj, st);
-    upload(b->d_ops, ops, st);
-    upload(b->d_op_inst, op_inst, st);
-    upload(b->d_stages, stages, st);
-    upload(b->d_phases, phases, st);
-    upload(b->d_phlist, phlist, st);
-    upload(b->d_dpool, dpool, st);
-    upload(b->d_btab, btab, st);
-    upload(b->d_qang, qang, st);
-    upload(b->d_terms, terms, st);
-    upload(b->d_slot_pidx, slot_pidx, st);
-    upload(b->d_items, items, st);
-    {
-      std::vector<double> m(mats.size() * 2), q(qtab.size() * 2);
-      for (size_t i = 0; i < mats.size(); ++i) { m[2 * i] = mats[i].real(); m[2 * i + 1] = mats[i].imag(); }
-      for (size_t i = 0; i < qtab.size(); ++i) { q[2 * i] = qtab[i].real(); q[2 * i + 1] = qtab[i].imag(); }
-      if (b->dbl) {
-        upload(b->d_matc, m, st);
-        upload(b->d_qtab, q, st);
-        upload_complex<double>(b->d_ctab, ctab, true, st);
-      } else {
-        upload(b->d_matc, std::vector<float>(m.begin(), m.end()), st);
-        upload(b->d_qtab, std::vector<float>(q.begin(), q.end()), st);
-        upload_complex<float>(b->d_ctab, ctab, false, st);
-      }
-    }
-    const size_t esz = b->dbl ? 16 : 8;
-    check_mem(size_t(state_elems) * esz + size_t(gp_elems) * 8);
-    b->d_states.ensure(size_t(state_elems) * esz + 16);
-    b->d_params.ensure(sizeof(double) * std::max(params, 1));
-    b->d_gpart.ensure(sizeof(double) * std::max<int64_t>(gp_elems, 1));
-    b->d_slot_sum.ensure(sizeof(double) * std::max(slots, 1));
-    b->d_epart.ensure(sizeof(double) * std::max(chunks, 1));
-    b->d_energies.ensure(sizeof(double) * count);
-    b->d_grads.ensure(sizeof(double) * std::max(params, 1));
-    hipck(hipHostMalloc((void**)&b->h_params, sizeof(double) * std::max(params, 1), hipHostMallocDefault),
-          "hipHostMalloc");
-    hipck(hipHostMalloc((void**)&b->h_energies, sizeof(double) * count, hipHostMallocDefault), "hipHostMalloc");
-    hipck(hipHostMalloc((void**)&b->h_grads, sizeof(double) * std::max(params, 1), hipHostMallocDefault),
-          "hipHostMalloc");
-    hipck(hipStreamSynchronize(st), "sync");
-    BatchArgs& a = b->args;
-    a.insts = b->d_insts.as<BatchInst>();
-    a.count = count;
-    a.geoms = b->d_geoms.as<PassGeom>();
-    a.geoms_adj = b->d_geoms_adj.as<PassGeom>();
-    a.dp.ops = b->d_ops.as<TileOp>();
-    a.dp.stages = b->d_stages.as<StageRec>();
-    a.dp.matc = b->d_matc.p;
-    a.dp.phases = b->d_phases.as<PhaseRec>();
-    a.dp.phlist = b->d_phlist.as<int32_t>();
-    a.dp.dpool = b->d_dpool.as<double>();
-    a.dp.btab = b->d_btab.as<double>();
-    a.dp.qtab = b->d_qtab.p;
-    a.dp.ctab = b->d_ctab.p;
-    a.dp.qang = b->d_qang.as<double>();
-    a.op_inst = b->d_op_inst.as<int32_t>();
-    a.nops_total = (int)ops.size();
-    a.states = b->d_states.p;
-    a.params = b->d_params.as<double>();
-    a.terms = b->d_terms.as<PauliTermDev>();
-    a.slot_pidx = b->d_slot_pidx.as<int32_t>();
-    a.gpart = b->d_gpart.as<double>();
-    a.slot_sum = b->d_slot_sum.as<double>();
-    a.epart = b->d_epart.as<double>();
-    a.energies = b->d_energies.as<double>();
-    a.grads = b->d_grads.as<double>();
+    batch_build(b.get());
     *out = b.release();
   });
 }
@@ -1901,47 +1933,63 @@ void batch_enqueue(qs_batch* b, bool grads) {
 }
 }  // namespace
 
+namespace {
+// One run: parameters in, graph replay (captured on the first run of each
+// kind; profiled runs launch eagerly so that their kernels are timed),
+// results out.
+void batch_run_impl(qs_batch* b, const double* params_packed, double* energies, double* grads) {
+  const bool want = grads != nullptr;
+  hipck(hipStreamSynchronize(b->stream), "sync");  // the previous run's copies have landed
+  if (b->nparams > 0) std::memcpy(b->h_params, params_packed, sizeof(double) * b->nparams);
+  if (!b->exec[want] && !g_prof) {
+    hipStream_t st = b->stream;
+    hipck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      batch_enqueue(b, want);
+    } catch (...) {
+      hipGraph_t gbad = nullptr;
+      (void)hipStreamEndCapture(st, &gbad);
+      if (gbad) (void)hipGraphDestroy(gbad);
+      throw;
+    }
+    hipck(hipStreamEndCapture(st, &b->graph[want]), "end capture");
+    hipck(hipGraphInstantiate(&b->exec[want], b->graph[want], nullptr, nullptr, 0), "graph instantiate");
+  }
+  if (b->exec[want] && !g_prof) hipck(hipGraphLaunch(b->exec[want], b->stream), "graph launch");
+  else batch_enqueue(b, want);
+  hipck(hipStreamSynchronize(b->stream), "sync");
+  std::memcpy(energies, b->h_energies, sizeof(double) * b->count);
+  if (want && b->nparams > 0) std::memcpy(grads, b->h_grads, sizeof(double) * b->nparams);
+}
+
+void batch_release(qs_batch* b) {
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (int w = 0; w < 2; ++w) {
+    if (b->exec[w]) (void)hipGraphExecDestroy(b->exec[w]);
+    if (b->graph[w]) (void)hipGraphDestroy(b->graph[w]);
+    b->exec[w] = nullptr;
+    b->graph[w] = nullptr;
+  }
+  if (b->h_params) (void)hipHostFree(b->h_params);
+  if (b->h_energies) (void)hipHostFree(b->h_energies);
+  if (b->h_grads) (void)hipHostFree(b->h_grads);
+  b->h_params = b->h_energies = b->h_grads = nullptr;
+}
+}  // namespace
+
 qs_status qs_batch_run(qs_batch* b, const double* params_packed, double* energies, double* grads) {
   return guard([&] {
     if (!b) fail(QS_E_INVALID, "null batch");
     if (b->nparams > 0 && !params_packed) fail(QS_E_INVALID, "null params");
     if (!energies) fail(QS_E_INVALID, "null energies");
-    const bool want = grads != nullptr;
-    hipck(hipStreamSynchronize(b->stream), "sync");  // the previous run's copies have landed
-    if (b->nparams > 0) std::memcpy(b->h_params, params_packed, sizeof(double) * b->nparams);
-    if (!b->exec[want] && !g_prof) {
-      hipStream_t st = b->stream;
-      hipck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
-      try {
-        batch_enqueue(b, want);
-      } catch (...) {
-        hipGraph_t gbad = nullptr;
-        (void)hipStreamEndCapture(st, &gbad);
-        if (gbad) (void)hipGraphDestroy(gbad);
-        throw;
-      }
-      hipck(hipStreamEndCapture(st, &b->graph[want]), "end capture");
-      hipck(hipGraphInstantiate(&b->exec[want], b->graph[want], nullptr, nullptr, 0), "graph instantiate");
-    }
-    if (b->exec[want] && !g_prof) hipck(hipGraphLaunch(b->exec[want], b->stream), "graph launch");
-    else batch_enqueue(b, want);  // profiled runs launch eagerly so that their kernels are timed
-    hipck(hipStreamSynchronize(b->stream), "sync");
-    std::memcpy(energies, b->h_energies, sizeof(double) * b->count);
-    if (want && b->nparams > 0) std::memcpy(grads, b->h_grads, sizeof(double) * b->nparams);
+    batch_run_impl(b, params_packed, energies, grads);
   });
 }
 
 qs_status qs_batch_destroy(qs_batch* b) {
   return guard([&] {
     if (!b) return;
-    if (b->stream) (void)hipStreamSynchronize(b->stream);
-    for (int w = 0; w < 2; ++w) {
-      if (b->exec[w]) (void)hipGraphExecDestroy(b->exec[w]);
-      if (b->graph[w]) (void)hipGraphDestroy(b->graph[w]);
-    }
-    if (b->h_params) (void)hipHostFree(b->h_params);
-    if (b->h_energies) (void)hipHostFree(b->h_energies);
-    if (b->h_grads) (void)hipHostFree(b->h_grads);
+    batch_release(b);
     hipStream_t st = b->own_stream ? b->stream : nullptr;
     delete b;
     if (st) (void)hipStreamDestroy(st);
@@ -2128,6 +2176,122 @@ qs_status qs_autotune(qs_circuit* c, qs_state* s, const double* params, const ch
     }
     compile_with(c, best, dbl, s->stream);
     cache_append(cache_path, key, best, best_ms);
+  });
+}
+
+// Per size class (the instances with one qubit count), time candidate
+// options on a batch of that class alone -- each candidate's launch
+// sequence captured and replayed as a graph -- keep the fastest whose
+// energies and gradients agree with the default's (1e-4 complex64, 1e-9
+// complex128), then rebuild the whole batch with each instance's choice.
+qs_status qs_batch_autotune(qs_batch* b, const double* params_packed, const char* cache_path) {
+  return guard([&] {
+    if (!b) fail(QS_E_INVALID, "null batch");
+    if (b->nparams > 0 && !params_packed) fail(QS_E_INVALID, "null params");
+    std::vector<int> poff(b->count + 1, 0);
+    for (int i = 0; i < b->count; ++i) poff[i + 1] = poff[i] + b->circs[i]->hc.nparams;
+    std::map<int, std::vector<int>> classes;
+    for (int i = 0; i < b->count; ++i) classes[b->circs[i]->hc.n].push_back(i);
+    std::vector<TuneChoice> cands = {{0, 0, -1, 0, 0}, {0, 0, -1, 0, 1}, {0, 0, -1, 5, 0},
+                                     {10, 0, -1, 0, 0}, {11, 0, -1, 0, 0}, {0, 2, -1, 0, 0}};
+    const double tol = b->dbl ? 1e-9 : 1e-4;
+    int dev = 0;
+    hipck(hipGetDevice(&dev), "hipGetDevice");
+    hipDeviceProp_t pr;
+    hipck(hipGetDeviceProperties(&pr, dev), "hipGetDeviceProperties");
+    std::string arch(pr.gcnArchName);
+    for (char& ch : arch)
+      if (ch == ' ') ch = '_';
+    hipEvent_t e0, e1;
+    hipck(hipEventCreate(&e0), "hipEventCreate");
+    hipck(hipEventCreate(&e1), "hipEventCreate");
+    struct EvFree {
+      hipEvent_t a, b;
+      ~EvFree() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } evfree{e0, e1};
+    for (auto& [n, members] : classes) {
+      uint64_t h = 1469598103934665603ull;
+      for (int i : members) h = (h ^ circuit_hash(b->circs[i]->hc)) * 1099511628211ull;
+      char kb[256];
+      std::snprintf(kb, sizeof kb, "batch-class n=%d count=%zu dtype=%s device=%s hash=%016llx", n, members.size(),
+                    b->dbl ? "c128" : "c64", arch.c_str(), (unsigned long long)h);
+      const std::string key = kb;
+      TuneChoice best = cands[0];
+      if (!cache_lookup(cache_path, key, &best)) {
+        qs_batch sub;
+        sub.count = (int)members.size();
+        sub.dbl = b->dbl;
+        sub.stream = b->stream;
+        std::vector<double> P;
+        for (int i : members) {
+          sub.circs.push_back(b->circs[i]);
+          sub.obs.push_back(b->obs[i]);
+          P.insert(P.end(), params_packed + poff[i], params_packed + poff[i + 1]);
+        }
+        struct SubFree {
+          qs_batch* s;
+          ~SubFree() { batch_release(s); }
+        } subfree{&sub};
+        std::vector<double> E0, G0, E(sub.count), G(std::max<size_t>(P.size(), 1));
+        double best_ms = 1e300;
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+          sub.opts.assign(sub.count, opts_of(cands[ci]));
+          try {
+            batch_build(&sub);
+          } catch (const Fail&) {
+            if (ci == 0) throw;
+            continue;  // a tiling this class cannot use
+          } catch (const std::exception&) {
+            if (ci == 0) throw;
+            continue;
+          }
+          batch_run_impl(&sub, P.data(), E.data(), G.data());
+          if (ci == 0) {
+            E0 = E;
+            G0 = G;
+          } else {
+            double d = 0;
+            for (size_t k = 0; k < E.size(); ++k) d = std::max(d, std::fabs(E[k] - E0[k]));
+            for (size_t k = 0; k < P.size(); ++k) d = std::max(d, std::fabs(G[k] - G0[k]));
+            if (!(d < tol)) continue;
+          }
+          double ms = 1e300;
+          for (int rep = 0; rep < 3; ++rep) {
+            hipck(hipEventRecord(e0, sub.stream), "hipEventRecord");
+            hipck(hipGraphLaunch(sub.exec[1], sub.stream), "graph launch");
+            hipck(hipEventRecord(e1, sub.stream), "hipEventRecord");
+            hipck(hipEventSynchronize(e1), "hipEventSynchronize");
+            float f = 0;
+            hipck(hipEventElapsedTime(&f, e0, e1), "hipEventElapsedTime");
+            ms = std::min(ms, (double)f);
+          }
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = cands[ci];
+          }
+        }
+        cache_append(cache_path, key, best, best_ms);
+      }
+      for (int i : members) b->opts[i] = opts_of(best);
+    }
+    batch_build(b);
+  });
+}
+
+qs_status qs_batch_choice(const qs_batch* b, int32_t i, qs_tune* out) {
+  return guard([&] {
+    if (!b || !out) fail(QS_E_INVALID, "null argument");
+    if (i < 0 || i >= b->count) fail(QS_E_INVALID, "instance index out of range");
+    const TuneOpts& o = b->opts[i];
+    std::memset(out, 0, sizeof *out);
+    out->tile_bits = o.tile_bits;
+    out->fuse_k = o.fuse_k;
+    out->use_mfma = o.use_mfma;
+    out->low_bits = o.low_bits;
+    out->lane_ops = o.lane_ops ? 1 : 0;
   });
 }
 

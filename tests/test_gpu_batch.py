@@ -79,3 +79,30 @@ def test_full_512_instance_batch_sampled_against_oracle(api):
         e_ref, g_ref = ograd.adjoint(n, spec, p, terms)
         assert abs(E[i] - e_ref) < 2e-4
         assert np.max(np.abs(G[offs[i]:offs[i + 1]] - g_ref)) < 2e-4
+
+
+def test_batch_autotune_per_size_class(api, tmp_path):
+    banner("batch autotune")
+    insts = qsynth.batch_instances(seed=5, count=24, nmin=8, nmax=15, dmin=2, dmax=6)
+    b, params = build(api, insts)
+    E0, G0 = b.run(params)
+    cache = str(tmp_path / "batch_tune.txt")
+    b.autotune(params, cache)
+    lines = open(cache).read().strip().splitlines()
+    classes = sorted({n for n, _, _, _ in insts})
+    assert len(lines) == len(classes) and all(ln.startswith("batch-class n=") for ln in lines)
+    for i, (n, _, _, _) in enumerate(insts):
+        ch = b.choice(i)
+        assert set(ch) == {"tile_bits", "fuse_k", "use_mfma", "low_bits", "lane_ops"}
+        # one choice per size class
+        assert ch == b.choice(next(j for j, it in enumerate(insts) if it[0] == n))
+    E1, G1 = b.run(params)  # rebuilt batch, fresh graphs
+    assert np.max(np.abs(E1 - E0)) < 1e-4 and np.max(np.abs(G1 - G0)) < 1e-4
+    off = 0
+    for i, (n, spec, p, terms) in enumerate(insts):
+        if i % 6 == 0:
+            e_ref, g_ref = ograd.adjoint(n, spec, p, terms)
+            assert abs(E1[i] - e_ref) < 2e-4 and np.max(np.abs(G1[off:off + p.size] - g_ref)) < 2e-4
+        off += p.size
+    b.autotune(params, cache)  # every class from the cache: nothing appended
+    assert len(open(cache).read().strip().splitlines()) == len(classes)
