@@ -149,7 +149,7 @@ template <typename T> void upload_complex(DBuf& d, const std::vector<cd>& v, boo
 }
 
 struct DevPlanBuf {
-  DBuf ops, mat, dpool, phases, qtab, qang, stages, phlist, btab, matc, ctab;
+  DBuf ops, sops, mat, dpool, phases, qtab, qang, stages, phlist, btab, matc, ctab;
   bool has_rot = false;
   bool has_scaled = false;
   DevPlan view;
@@ -180,6 +180,7 @@ struct DevPlanBuf {
       geoms_adj.push_back(g);
     }
     upload(ops, all, s);
+    upload(sops, staged_records(all, p.phases), s);
     std::vector<double> m(p.matpool.size() * 2);
     for (size_t i = 0; i < p.matpool.size(); ++i) {
       m[2 * i] = p.matpool[i].real();
@@ -221,6 +222,7 @@ struct DevPlanBuf {
       upload(qtab, q, s);
     }
     view.ops = ops.as<TileOp>();
+    view.sops = sops.as<StagedOp>();
     view.mat = mat.as<double>();
     view.dpool = dpool.as<double>();
     view.phases = phases.as<PhaseRec>();
@@ -320,7 +322,7 @@ struct qs_batch {
   };
   std::vector<Level> fwd, adj;
   int chunk_off = 0, nchunks = 0;
-  DBuf d_insts, d_geoms, d_geoms_adj, d_ops, d_stages, d_matc, d_phases, d_phlist, d_dpool, d_btab, d_qtab, d_qang, d_ctab;
+  DBuf d_insts, d_geoms, d_geoms_adj, d_ops, d_sops, d_stages, d_matc, d_phases, d_phlist, d_dpool, d_btab, d_qtab, d_qang, d_ctab;
   DBuf d_terms, d_slot_pidx, d_op_inst, d_items, d_states, d_params, d_gpart, d_slot_sum, d_epart, d_energies,
       d_grads;
   double* h_params = nullptr;
@@ -1669,6 +1671,7 @@ void batch_build(qs_batch* b) {
   if (b->h_grads) (void)hipHostFree(b->h_grads);
   b->h_params = b->h_energies = b->h_grads = nullptr;
   std::vector<TileOp> ops;
+  std::vector<StagedOp> sops;
   std::vector<StageRec> stages;
   std::vector<cd> mats;
   std::vector<PhaseRec> phases;
@@ -1735,6 +1738,11 @@ void batch_build(qs_batch* b) {
     }
     in.nops = nops;
     in.tbits = std::max(tbits, 0);
+    {  // this instance's op records, against its own phase records
+      const std::vector<TileOp> mine(ops.begin() + in.ops_base, ops.end());
+      const std::vector<StagedOp> r = staged_records(mine, p.phases);
+      sops.insert(sops.end(), r.begin(), r.end());
+    }
     stages.insert(stages.end(), p.stages.begin(), p.stages.end());
     mats.insert(mats.end(), p.matpool.begin(), p.matpool.end());
     phases.insert(phases.end(), p.phases.begin(), p.phases.end());
@@ -1800,6 +1808,7 @@ void batch_build(qs_batch* b) {
   upload(b->d_geoms, b->geoms, st);
   upload(b->d_geoms_adj, b->geoms_adj, st);
   upload(b->d_ops, ops, st);
+  upload(b->d_sops, sops, st);
   upload(b->d_op_inst, op_inst, st);
   upload(b->d_stages, stages, st);
   upload(b->d_phases, phases, st);
@@ -1845,6 +1854,7 @@ void batch_build(qs_batch* b) {
   a.geoms = b->d_geoms.as<PassGeom>();
   a.geoms_adj = b->d_geoms_adj.as<PassGeom>();
   a.dp.ops = b->d_ops.as<TileOp>();
+  a.dp.sops = b->d_sops.as<StagedOp>();
   a.dp.stages = b->d_stages.as<StageRec>();
   a.dp.matc = b->d_matc.p;
   a.dp.phases = b->d_phases.as<PhaseRec>();

@@ -11,6 +11,7 @@ namespace qs {
 // Device copies of a plan's pools.
 struct DevPlan {
   const TileOp* ops = nullptr;
+  const StagedOp* sops = nullptr;  // op records of staged passes (same index as ops)
   const double* mat = nullptr;    // complex128 interleaved
   const double* dpool = nullptr;  // phase polynomials
   const PhaseRec* phases = nullptr;

@@ -1520,12 +1520,17 @@ __device__ __forceinline__ double rgrad(const C* ps, const C* la, uint32_t creg,
   return acc;
 }
 
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Im <lambda| P psi> over the 8 pairs of slot K, P a Pauli known at compile
 // time, accumulated in the state's precision (per thread: 16 amplitudes)
 template <int K, int PAULI, typename C>
 __device__ __forceinline__ auto rgrad_fast(const C* ps, const C* la) {
   using T = decltype(C().x);
-  T acc = 0;
+  // two FMA chains, one per amplitude of the pair (four FMAs per pair)
+  T acc0 = 0, acc1 = 0;
+  bool first = true;
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
     if (e & (1 << K)) continue;
@@ -1535,9 +1540,18 @@ __device__ __forceinline__ auto rgrad_fast(const C* ps, const C* la) {
     if (PAULI == 1) { q0r = p1.x; q0i = p1.y; q1r = p0.x; q1i = p0.y; }
     else if (PAULI == 2) { q0r = p1.y; q0i = -p1.x; q1r = -p0.y; q1i = p0.x; }
     else { q0r = p0.x; q0i = p0.y; q1r = -p1.x; q1i = -p1.y; }
-    acc += l0.x * q0i - l0.y * q0r + l1.x * q1i - l1.y * q1r;
+    if (first) {
+      acc0 = l0.x * q0i;
+      acc1 = l1.x * q1i;
+      first = false;
+    } else {
+      acc0 = fma_t(l0.x, q0i, acc0);
+      acc1 = fma_t(l1.x, q1i, acc1);
+    }
+    acc0 = fma_t(-l0.y, q0r, acc0);
+    acc1 = fma_t(-l1.y, q1r, acc1);
   }
-  return acc;
+  return acc0 + acc1;
 }
 
 template <typename C>
@@ -1630,7 +1644,7 @@ constexpr int kEnRow = kMaxTileBits + 1;  // exp(i angle) of tile bit b's coeffi
 template <typename R, bool TWO, int NLD, bool GUARD, bool CTRL>
 __device__ __forceinline__ void pass_body(
     typename CT<R>::C* __restrict__ psi, typename CT<R>::C* __restrict__ lam, const PassGeom& g,
-    const TileOp* __restrict__ ops, const StageRec* __restrict__ stages,
+    const TileOp* __restrict__ ops, const StagedOp* __restrict__ sops, const StageRec* __restrict__ stages,
     const typename CT<R>::C* __restrict__ matc, const PhaseRec* __restrict__ phases,
     const int32_t* __restrict__ phlist, const double* __restrict__ dpool, const double* __restrict__ btab,
     const typename CT<R>::C* __restrict__ qtab, const double* __restrict__ qang,
@@ -1887,18 +1901,17 @@ __device__ __forceinline__ void pass_body(
         // multiple of pi, so the parity of a sum is the XOR of the parities:
         // tile part from phS, group part from the bit-sliced table (one
         // 64-bit word per wave and slice: scalar loads)
-        auto sign_mask = [&](const TileOp& op, const StageRec& sr, int grp, uint32_t jgl) -> uint32_t {
-          const int p = op.pidx;
-          const PhaseRec rec = phases[op.aux];
+        auto sign_mask = [&](const StagedOp& so, const StageRec& sr, int grp, uint32_t jgl) -> uint32_t {
+          const int p = so.ph & 0xFF;
           const int nw = ((M >> NR) + 63) >> 6;
           const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)grp >> 6);
-          const uint64_t* sb = reinterpret_cast<const uint64_t*>(btab + rec.bt_off) + wv;
+          const uint64_t* sb = reinterpret_cast<const uint64_t*>(btab + so.tab) + wv;
           const uint32_t ln = (uint32_t)grp & 63u;
           auto gbit = [&](int sl) { return (uint32_t)(sb[sl * nw] >> ln) & 1u; };
           const uint32_t ts = sm.phS[p];
           uint32_t S;
-          if (op.flags & 2u) {
-            const int kbs = op.b[0];
+          if ((so.ph >> 11) & 1) {
+            const int kbs = (so.ph >> 8) & 3;
             const int rbk = kbs == 0 ? sr.rb[0] : kbs == 1 ? sr.rb[1] : kbs == 2 ? sr.rb[2] : sr.rb[3];
             S = (((ts >> rbk) ^ gbit(1 + kbs)) & 1u) ? slot_pattern(kbs) : 0u;
           } else {
@@ -1908,19 +1921,18 @@ __device__ __forceinline__ void pass_body(
             if (((ts >> sr.rb[2]) ^ gbit(3)) & 1u) S ^= 0xF0F0u;
             if (((ts >> sr.rb[3]) ^ gbit(4)) & 1u) S ^= 0xFF00u;
           }
-          return S ^ (uint32_t)rec.wr_sign;
+          return S ^ ((uint32_t)so.ph >> 16);
         };
         // general phase: factor of register element e = exp(i theta_tile) *
         // exp(i beta_0) * prod_{tile bits r in jg} EN[r] * prod_{k in e}
         // EN[rb_k] exp(i beta_k) * exp(i Q_R(e)), every factor from a table
-        auto phase_general = [&](const TileOp& op, const StageRec& sr, int grp, uint32_t jgl) {
-          const int p = op.pidx;
-          const PhaseRec rec = phases[op.aux];
-          const C* bc = ctab + rec.ctab_off + grp * (NR + 1);
-          const C* wc = ctab + rec.ctab_off + (rec.ctab_n - NE);
+        auto phase_general = [&](const StagedOp& so, const StageRec& sr, int grp, uint32_t jgl) {
+          const int p = so.ph & 0xFF;
+          const C* bc = ctab + so.tab + grp * (NR + 1);
+          const C* wc = ctab + so.tab + (so.mat - NE);
           auto EN = [&](int b) { return en[p * kEnRow + b]; };
           auto B = [&](int k) { return TWO ? cconj(bc[k]) : bc[k]; };
-          const bool wtriv = rec.wr_trivial != 0;
+          const bool wtriv = (so.ph >> 10) & 1;
           C f = cmul(EN(kMaxTileBits), B(0));
           for (uint32_t r = jgl; r; r &= r - 1) f = cmul(f, EN(__builtin_ctz(r)));
           const C F0 = cmul(EN(sr.rb[0]), B(1));
@@ -1952,15 +1964,14 @@ __device__ __forceinline__ void pass_body(
           f = cmul(f, cconj(F0)); apply(8, f);
         };
         // every term holds register slot KBS: factor 1 where that bit is 0
-        auto phase_single = [&](const TileOp& op, const StageRec& sr, int grp, auto kbs_c) {
+        auto phase_single = [&](const StagedOp& so, const StageRec& sr, int grp, auto kbs_c) {
           constexpr int KBS = decltype(kbs_c)::value;
-          const int p = op.pidx;
-          const PhaseRec rec = phases[op.aux];
-          const C* bc = ctab + rec.ctab_off + grp * (NR + 1);
-          const C* wc = ctab + rec.ctab_off + (rec.ctab_n - NE);
+          const int p = so.ph & 0xFF;
+          const C* bc = ctab + so.tab + grp * (NR + 1);
+          const C* wc = ctab + so.tab + (so.mat - NE);
           const C b = TWO ? cconj(bc[1 + KBS]) : bc[1 + KBS];
           const C F = cmul(en[p * kEnRow + sr.rb[KBS]], b);
-          const bool wtriv = rec.wr_trivial != 0;
+          const bool wtriv = (so.ph >> 10) & 1;
 #pragma unroll
           for (int e = 0; e < NE; ++e) {
             if (!((e >> KBS) & 1)) continue;
@@ -1969,46 +1980,41 @@ __device__ __forceinline__ void pass_body(
             if (TWO) cmul_ip(w[e], fe);
           }
         };
-        for (int oi = 0; oi < st.nops; ++oi) {
-          const int o = op0 + st.op0 + (TWO ? st.nops - 1 - oi : oi);
-          const int kind = ops[o].kind;
-          const uint32_t cin = ops[o].cin, creg = ops[o].creg;
-          const bool uact = (base & ops[o].cout) == ops[o].cout;  // uniform
+        // the stage's op records in the order they run, each fetched one op
+        // ahead: its scalar loads are in flight while the previous op runs
+        const StagedOp* __restrict__ sop = sops + op0 + st.op0;
+        const int nso = st.nops;
+        StagedOp cur = sop[TWO ? nso - 1 : 0], nx;
+        for (int oi = 0; oi < nso; ++oi, cur = nx) {
+          nx = sop[TWO ? (nso - 2 - oi > 0 ? nso - 2 - oi : 0) : (oi + 1 < nso ? oi + 1 : oi)];
+          const uint32_t cin = cur.ctl & 0xFFFFu, creg = cur.ctl >> 16;
+          const uint64_t cout = ((uint64_t)cur.cout_hi << 32) | cur.cout_lo;
+          const bool uact = (base & cout) == cout;  // uniform
           bool act = valid && uact;
           if (cin) act = act && ((jg & cin) == cin);
-          if (TWO && kind == OP_ROT && ops[o].gslot >= 0) {
+          if (TWO && cur.grad >= 0) {
             // per-thread partial, summed across the wave with DPP; lane 63 adds
             // the wave's total to its slot (a single writer per slot)
             using T = decltype(C().x);
+            const int gk = (cur.grad >> 12) & 3, gp = (cur.grad >> 8) & 3;
             T pg = 0;
             if (creg == 0 && cin == 0) {
-              if (valid) pg = (T)rgrad_fast_any(v, w, ops[o].b[0], ops[o].pauli);
+              if (valid) pg = (T)rgrad_fast_any(v, w, gk, gp);
             } else if (CTRL && act) {
-              pg = (T)rgrad_any(v, w, ops[o].b[0], creg, ops[o].pauli);
+              pg = (T)rgrad_any(v, w, gk, creg, gp);
             }
             if (!uact) pg = 0;
             pg = wave_sum_rows(row_sum(pg));
-            if ((tid & 63) == 63) gacc[ops[o].aux * (kThreads / 64) + (tid >> 6)] += (double)pg;
+            // no returned value: nothing waits on the LDS add
+            if ((tid & 63) == 63) atomicAdd(&gacc[(cur.grad & 0xFF) * (kThreads / 64) + (tid >> 6)], (double)pg);
           }
           if (!uact) continue;
           if (cin == 0 && creg == 0) {
             // one flat switch over a uniform opcode with compile-time slots:
             // straight-line cases keep the register array in place
-            int opc;
-            if ((kind == OP_DENSE1 || kind == OP_ROT) && (ops[o].flags & 32u))  // lane ops
-              opc = 40 + 4 * ((ops[o].flags & 16u) ? 2 : (ops[o].flags & 8u) ? 3 : (ops[o].flags & 1u) ? 1 : 0) +
-                    ops[o].b[0];
-            else if (kind == OP_DENSE1 || kind == OP_ROT)
-              opc = ((ops[o].flags & 16u) ? 24 : (ops[o].flags & 8u) ? 28 : (ops[o].flags & 1u) ? 4 : 0) + ops[o].b[0];
-            else if (kind == OP_DENSE2) {
-              const int kh = ops[o].b[0], kl = ops[o].b[1];
-              opc = 8 + (kh == 1 ? 0 : kh == 2 ? 1 + kl : 3 + kl);
-            } else if (kind == OP_PHASE && (ops[o].flags & 4u)) opc = 14;
-            else if (kind == OP_PHASE) opc = (ops[o].flags & 2u) ? 20 + ops[o].b[0] : 19;
-            else opc = -1;
-            const C* m1 = matc + ops[o].mat + (TWO ? 4 : 0);
-            const C* m2 = matc + ops[o].mat + (TWO ? 16 : 0);
-            switch (opc) {
+            const C* m1 = matc + cur.mat + (TWO ? 4 : 0);
+            const C* m2 = matc + cur.mat + (TWO ? 16 : 0);
+            switch (cur.opc) {
               case 0: op1<0, false, TWO>(v, w, m1); break;
               case 1: op1<1, false, TWO>(v, w, m1); break;
               case 2: op1<2, false, TWO>(v, w, m1); break;
@@ -2023,12 +2029,12 @@ __device__ __forceinline__ void pass_body(
               case 11: op2<3, 0, TWO>(v, w, m2); break;
               case 12: op2<3, 1, TWO>(v, w, m2); break;
               case 13: op2<3, 2, TWO>(v, w, m2); break;
-              case 14: apply_signs<TWO>(v, w, sign_mask(ops[o], st, grp, jg)); break;
-              case 19: phase_general(ops[o], st, grp, jg); break;
-              case 20: phase_single(ops[o], st, grp, std::integral_constant<int, 0>()); break;
-              case 21: phase_single(ops[o], st, grp, std::integral_constant<int, 1>()); break;
-              case 22: phase_single(ops[o], st, grp, std::integral_constant<int, 2>()); break;
-              case 23: phase_single(ops[o], st, grp, std::integral_constant<int, 3>()); break;
+              case 14: apply_signs<TWO>(v, w, sign_mask(cur, st, grp, jg)); break;
+              case 19: phase_general(cur, st, grp, jg); break;
+              case 20: phase_single(cur, st, grp, std::integral_constant<int, 0>()); break;
+              case 21: phase_single(cur, st, grp, std::integral_constant<int, 1>()); break;
+              case 22: phase_single(cur, st, grp, std::integral_constant<int, 2>()); break;
+              case 23: phase_single(cur, st, grp, std::integral_constant<int, 3>()); break;
               case 24: op1d<0, TWO>(v, w, m1); break;
               case 25: op1d<1, TWO>(v, w, m1); break;
               case 26: op1d<2, TWO>(v, w, m1); break;
@@ -2059,27 +2065,26 @@ __device__ __forceinline__ void pass_body(
           }
           // controlled ops (register-slot or in-tile controls): predicated per
           // thread, compiled only into the variant for passes that hold them
-          if (!CTRL) continue;
-          if (kind == OP_DENSE1 || kind == OP_ROT) {
-            const int k = ops[o].b[0];
-            if (!act) continue;
-            const C* mp = matc + ops[o].mat + (TWO ? 4 : 0);
+          if (!CTRL || !act || cur.tab < 0) continue;
+          const int k0 = cur.tab & 15, k1 = (cur.tab >> 4) & 15;
+          if (!((cur.tab >> 9) & 1)) {
+            const C* mp = matc + cur.mat + (TWO ? 4 : 0);
             const C a = mp[0], b = mp[1], c = mp[2], d = mp[3];
-            if (ops[o].flags & 1u) {
-              r1_any<true>(v, k, a, b, c, d, creg);
-              if (TWO) r1_any<true>(w, k, a, b, c, d, creg);
+            if ((cur.tab >> 8) & 1) {
+              r1_any<true>(v, k0, a, b, c, d, creg);
+              if (TWO) r1_any<true>(w, k0, a, b, c, d, creg);
             } else {
-              r1_any<false>(v, k, a, b, c, d, creg);
-              if (TWO) r1_any<false>(w, k, a, b, c, d, creg);
+              r1_any<false>(v, k0, a, b, c, d, creg);
+              if (TWO) r1_any<false>(w, k0, a, b, c, d, creg);
             }
-          } else if (kind == OP_DENSE2) {
-            if (!act) continue;
-            const C* mp = matc + ops[o].mat + (TWO ? 16 : 0);
-            r2_any(v, ops[o].b[0], ops[o].b[1], mp, creg);
-            if (TWO) r2_any(w, ops[o].b[0], ops[o].b[1], mp, creg);
+          } else {
+            const C* mp = matc + cur.mat + (TWO ? 16 : 0);
+            r2_any(v, k0, k1, mp, creg);
+            if (TWO) r2_any(w, k0, k1, mp, creg);
           }
         }
-        if (SEQ) __syncthreads();  // every thread has read its lambda from the buffer
+        // (no barrier before the scatter in the two-state pass: every thread
+        // writes psi back to exactly the buffer entries it read lambda from)
         if (valid) {
           uint32_t ad = A;
 #pragma unroll
@@ -2129,7 +2134,7 @@ __device__ __forceinline__ void pass_body(
 template <typename R, bool TWO, int NLD, bool CTRL>
 __global__ __launch_bounds__(256) void k_tile2(
     typename CT<R>::C* __restrict__ psi, typename CT<R>::C* __restrict__ lam, const PassGeom g,
-    const TileOp* __restrict__ ops, const StageRec* __restrict__ stages,
+    const TileOp* __restrict__ ops, const StagedOp* __restrict__ sops, const StageRec* __restrict__ stages,
     const typename CT<R>::C* __restrict__ matc, const PhaseRec* __restrict__ phases,
     const int32_t* __restrict__ phlist, const double* __restrict__ dpool, const double* __restrict__ btab,
     const typename CT<R>::C* __restrict__ qtab, const double* __restrict__ qang,
@@ -2139,7 +2144,7 @@ __global__ __launch_bounds__(256) void k_tile2(
   __shared__ PassSmem sm;
   __shared__ typename CT<R>::C en[kMaxPhasePerPass * kEnRow];
   __shared__ double gacc[TWO ? kMaxGradPerPass * (kThreads / 64) : 1];
-  pass_body<R, TWO, NLD, false, CTRL>(psi, lam, g, ops, stages, matc, phases, phlist, dpool, btab, qtab, qang, scales,
+  pass_body<R, TWO, NLD, false, CTRL>(psi, lam, g, ops, sops, stages, matc, phases, phlist, dpool, btab, qtab, qang, scales,
                                 ctab, gpart, kGradStride, blockIdx.x * 4, blockIdx.x, gridDim.x, ntiles,
                                 __builtin_ctz(gridDim.x), sm, smem, en, gacc);
 }
@@ -2344,7 +2349,7 @@ __global__ __launch_bounds__(256) void k_batch_pass(const BatchArgs a, const Bat
   const PassGeom& g = (TWO ? a.geoms_adj : a.geoms)[in.pass0 + it.pass];
   const int64_t nt = 1ll << in.tbits;
   pass_body<R, TWO, NLD, true, CTRL>(
-      psi, lam, g, a.dp.ops + in.ops_base, a.dp.stages + in.st_base,
+      psi, lam, g, a.dp.ops + in.ops_base, a.dp.sops + in.ops_base, a.dp.stages + in.st_base,
       reinterpret_cast<const C*>(a.dp.matc) + in.mat_base, a.dp.phases + in.ph_base, a.dp.phlist + in.phl_base,
       a.dp.dpool + in.dp_base, a.dp.btab + in.bt_base, reinterpret_cast<const C*>(a.dp.qtab) + in.qt_base,
       a.dp.qang + in.qt_base, nullptr, reinterpret_cast<const C*>(a.dp.ctab) + in.ct_base, a.gpart + in.gp_off,
@@ -2470,11 +2475,11 @@ hipError_t launch_tile2_c(void* psi, void* psi2, const PassGeom& g, const DevPla
   if (e != hipSuccess) return e;
   if (two)
     hipLaunchKernelGGL((k_tile2<R, true, NLD, CTRL>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, (C*)psi2, g,
-                       dp.ops, dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab,
+                       dp.ops, dp.sops, dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab,
                        (const C*)dp.qtab, dp.qang, scales, (const C*)dp.ctab, gpart, nt);
   else
     hipLaunchKernelGGL((k_tile2<R, false, NLD, CTRL>), dim3(grid), dim3(kThreads), lds, s, (C*)psi, nullptr, g,
-                       dp.ops, dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab,
+                       dp.ops, dp.sops, dp.stages, (const C*)dp.matc, dp.phases, dp.phlist, dp.dpool, dp.btab,
                        (const C*)dp.qtab, dp.qang, scales, (const C*)dp.ctab, gpart, nt);
   return hipGetLastError();
 }

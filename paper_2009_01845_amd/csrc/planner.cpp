@@ -900,6 +900,55 @@ std::vector<cd> embed_gate(const Gate& g, const std::vector<int>& sup) {
 // qubits): consecutive fixed gates are multiplied into one dense matrix while
 // their joint support stays within K qubits; rotations with run-time angles
 // end a block and pass through.
+std::vector<StagedOp> staged_records(const std::vector<TileOp>& ops, const std::vector<PhaseRec>& phases) {
+  std::vector<StagedOp> out(ops.size());
+  for (size_t i = 0; i < ops.size(); ++i) {
+    const TileOp& op = ops[i];
+    StagedOp& r = out[i];
+    r.opc = -1;
+    r.ctl = (op.cin & 0xFFFFu) | (op.creg << 16);
+    r.cout_lo = (uint32_t)op.cout;
+    r.cout_hi = (uint32_t)(op.cout >> 32);
+    r.mat = op.mat;
+    r.grad = (op.kind == OP_ROT && op.gslot >= 0) ? (op.aux | (op.pauli << 8) | (op.b[0] << 12)) : -1;
+    r.ph = 0;
+    r.tab = 0;
+    const bool one = op.kind == OP_DENSE1 || op.kind == OP_ROT;
+    if (op.kind == OP_PHASE) {
+      const PhaseRec& rec = phases[op.aux];
+      const bool single = (op.flags & 2u) != 0;
+      r.ph = (op.pidx & 0xFF) | ((single ? op.b[0] & 3 : 0) << 8) | ((rec.wr_trivial ? 1 : 0) << 10) |
+             ((single ? 1 : 0) << 11) | (int32_t)((uint32_t)(rec.wr_sign & 0xFFFF) << 16);
+      if (op.flags & 4u) {
+        r.opc = 14;
+        r.tab = rec.bt_off;
+      } else {
+        r.opc = single ? 20 + op.b[0] : 19;
+        r.tab = rec.ctab_off;
+        r.mat = rec.ctab_n;
+      }
+      continue;
+    }
+    if (op.cin != 0 || op.creg != 0) {  // controlled: predicated path
+      const bool two = op.kind == OP_DENSE2;
+      r.tab = (one || two) ? (op.b[0] & 15) | ((two ? op.b[1] & 15 : 0) << 4) | (((op.flags & 1u) ? 1 : 0) << 8) |
+                                 ((two ? 1 : 0) << 9)
+                           : -1;
+      continue;
+    }
+    if (one && (op.flags & 32u)) {  // lane ops
+      const int form = (op.flags & 16u) ? 2 : (op.flags & 8u) ? 3 : (op.flags & 1u) ? 1 : 0;
+      r.opc = 40 + 4 * form + op.b[0];
+    } else if (one) {
+      r.opc = ((op.flags & 16u) ? 24 : (op.flags & 8u) ? 28 : (op.flags & 1u) ? 4 : 0) + op.b[0];
+    } else if (op.kind == OP_DENSE2) {
+      const int kh = op.b[0], kl = op.b[1];
+      r.opc = 8 + (kh == 1 ? 0 : kh == 2 ? 1 + kl : 3 + kl);
+    }
+  }
+  return out;
+}
+
 std::vector<Gate> fuse_gates(const std::vector<Gate>& in, int K) {
   std::vector<Gate> out;
   std::vector<int> sup;

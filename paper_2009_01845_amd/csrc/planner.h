@@ -127,6 +127,10 @@ PhasePoly ising_poly(int n, const double* J, const double* h);
 Plan plan_trotter(int n, bool dbl, const TuneOpts& opts, const PhasePoly* poly, int steps,
                   bool final_layer = false);
 
+// The op records of staged passes (StagedOp), one per op of `ops`, whose phase
+// ops index `phases` (the plan's phase records).  Ops of other passes get
+// records with opc = -1 and no gradient.
+std::vector<StagedOp> staged_records(const std::vector<TileOp>& ops, const std::vector<PhaseRec>& phases);
 // Greedy fusion of consecutive fixed gates into blocks of at most K qubits.
 std::vector<Gate> fuse_gates(const std::vector<Gate>& in, int K);
 

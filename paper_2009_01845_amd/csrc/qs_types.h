@@ -46,6 +46,21 @@ struct TileOp {
                      // bit 5 lane op (b[0] = lane bit 0..3 of the thread-group index, not a slot)
 };
 
+// The op record a staged pass walks, one per TileOp (same index), built on the
+// host from the TileOp and its phase record so that everything an op needs
+// arrives in one 32-byte load, issued one op ahead of its use.
+struct StagedOp {
+  int32_t opc;       // dispatch code of an uncontrolled op (-1: none; controlled ops use tab)
+  uint32_t ctl;      // in-tile controls cin (bits 0..15) | register-slot controls creg << 16
+  uint32_t cout_lo;  // controls on index bits outside the tile (all must be 1)
+  uint32_t cout_hi;
+  int32_t mat;       // 1-/2-qubit ops: matrix pool offset; general phase ops: ctab_n
+  int32_t grad;      // two-state gradient: LDS slot | pauli << 8 | register slot << 12; -1: none
+  int32_t ph;        // phase ops: per-pass slot p | kbs << 8 | wr_trivial << 10 | single-slot << 11 | wr_sign << 16
+  int32_t tab;       // sign ops: bt_off; general phase ops: ctab_off;
+                     // controlled ops: b[0] | b[1] << 4 | real << 8 | two-qubit << 9
+};
+
 constexpr int kRegBits = 4;            // register slots per thread in a staged pass
 constexpr int kMaxPhasePerPass = 14;   // phase ops whose tile terms are prepared per tile
 constexpr int kMaxGradPerPass = 64;    // parameterised rotations per pass (adjoint partials kept in LDS)
