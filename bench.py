@@ -140,11 +140,12 @@ def dense_blocks(n: int, seed: int = 11):
     return [qsynth.gate("MAT", t, mat=qsynth.haar_unitary(1 << len(t), rng)) for t in sets]
 
 
-def sweep(n: int, dt: str, only: str | None):
+def sweep(n: int, dt: str, only: str | None, all_bits: bool = False):
     """Per-kernel-kind table at n qubits: one JSON line per case with the
     device time per launch (HIP events on the launch stream), algorithmic
     GB/s and its fraction of 8 TB/s and of a device copy measured alongside;
-    matrix-core blocks also report TFLOP/s."""
+    matrix-core blocks also report TFLOP/s.  all_bits: the one-qubit case at
+    every index bit instead of seven of them."""
     import numpy as np
     import torch
 
@@ -188,7 +189,7 @@ def sweep(n: int, dt: str, only: str | None):
     Q = lambda bit: n - 1 - bit  # noqa: E731  (qubit holding index bit `bit`)
     hu = lambda k: qsynth.haar_unitary(1 << k, rng)  # noqa: E731
     cases = {}
-    for bit in (0, 5, 6, 11, 12, 20, n - 1):
+    for bit in (range(n) if all_bits else (0, 5, 6, 11, 12, 20, n - 1)):
         cases[f"haar1q_bit{bit}"] = [qsynth.gate("MAT", (Q(bit),), mat=hu(1))]
     cases["H_bit17"] = [qsynth.gate("H", (Q(17),))]
     cases["X_bit17"] = [qsynth.gate("X", (Q(17),))]
@@ -493,13 +494,14 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="per-kernel-kind table instead of the step (one line per case)")
     ap.add_argument("--sweep-dtype", default="c64")
     ap.add_argument("--sweep-only", default=None, help="run the sweep cases whose name contains this text")
+    ap.add_argument("--sweep-all-bits", action="store_true", help="the one-qubit sweep case at every index bit")
     ap.add_argument("--rows", action="store_true", help="the measurement rows M1-M7, one JSON line each")
     ap.add_argument("--rows-only", default=None, help="rows whose name contains this text (e.g. M4)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         sys.exit("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)")
     if args.sweep:
-        sweep(args.n, args.sweep_dtype, args.sweep_only)
+        sweep(args.n, args.sweep_dtype, args.sweep_only, args.sweep_all_bits)
         return
     if args.rows:
         rows(args.rows_only)

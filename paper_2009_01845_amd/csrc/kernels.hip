@@ -85,6 +85,33 @@ __device__ __forceinline__ void fma_self(float& a, float m, float t) {
 __device__ __forceinline__ void fma_self(double& a, double m, double t) {
   asm("v_fma_f64 %0, %0, %1, %2" : "+v"(a) : "v"(m), "v"(t));
 }
+// y = y + m * x and y = y - m * x, in the register of y
+__device__ __forceinline__ void fma_acc(float& y, float m, float x) {
+  asm("v_fma_f32 %0, %1, %2, %0" : "+v"(y) : "v"(m), "v"(x));
+}
+__device__ __forceinline__ void fma_acc(double& y, double m, double x) {
+  asm("v_fma_f64 %0, %1, %2, %0" : "+v"(y) : "v"(m), "v"(x));
+}
+__device__ __forceinline__ void fms_acc(float& y, float m, float x) {
+  asm("v_fma_f32 %0, -%1, %2, %0" : "+v"(y) : "v"(m), "v"(x));
+}
+__device__ __forceinline__ void fms_acc(double& y, double m, double x) {
+  asm("v_fma_f64 %0, -%1, %2, %0" : "+v"(y) : "v"(m), "v"(x));
+}
+// (x, y) <- plane rotation by phi of (x, y), |phi| <= pi/2, as three shears
+// x -= t y, y += s x, x -= t y with t = tan(phi/2), s = sin(phi): three
+// in-place FMAs instead of two multiplies and two FMAs.  NEG rotates by -phi.
+template <bool NEG, typename T> __device__ __forceinline__ void shear3(T& x, T& y, T t, T s) {
+  if (NEG) {
+    fma_acc(x, t, y);
+    fms_acc(y, s, x);
+    fma_acc(x, t, y);
+  } else {
+    fms_acc(x, t, y);
+    fma_acc(y, s, x);
+    fms_acc(x, t, y);
+  }
+}
 // v *= f
 template <typename C> __device__ __forceinline__ void cmul_ip(C& v, C f) {
   auto vx = v.x, vy = v.y;
@@ -1393,6 +1420,36 @@ __device__ __forceinline__ void r1x(C* v, C m00, C m01) {
     v[f].y = qy;
   }
 }
+// a Y (X = false) or X (X = true) rotation on slot K in three-shear form, up
+// to the sign (-1)^k of its angle reduction: a Y rotation turns (p.x, q.x)
+// and (p.y, q.y) by phi; an X rotation turns (p.y, q.x) by phi and (p.x, q.y)
+// by -phi
+template <int K, bool X, typename C, typename T>
+__device__ __forceinline__ void r1s(C* v, T t, T s) {
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    if (e & (1 << K)) continue;
+    const int f = e | (1 << K);
+    auto px = v[e].x, py = v[e].y, qx = v[f].x, qy = v[f].y;
+    if (X) {
+      shear3<false>(py, qx, t, s);
+      shear3<true>(px, qy, t, s);
+    } else {
+      shear3<false>(px, qx, t, s);
+      shear3<false>(py, qy, t, s);
+    }
+    v[e].x = px;
+    v[e].y = py;
+    v[f].x = qx;
+    v[f].y = qy;
+  }
+}
+template <int K, bool X, bool TWO, typename C>
+__device__ __forceinline__ void op1s(C* v, C* w, const C* __restrict__ sp) {
+  const C ts = sp[0];
+  r1s<K, X>(v, ts.x, ts.y);
+  if (TWO) r1s<K, X>(w, ts.x, ts.y);
+}
 template <int K, typename C>
 __device__ __forceinline__ void r1d(C* v, C d0, C d1) {
 #pragma unroll
@@ -1845,6 +1902,7 @@ __device__ __forceinline__ void pass_body(
     if (PF && t + t_step < ntiles) QS_PREFETCH(t + t_step);  // the LDS copies of pre are done
 #undef QS_PREFETCH
 
+    bool neg = false;  // odd count of shear-form rotations with sign -1: negate after the last stage
     for (int si = 0; si < nst; ++si) {
       const StageRec st = stages[st0 + (TWO ? nst - 1 - si : si)];
       // register element e sits at tile index jg | jr(e), jr(e) = the bits of e
@@ -2014,6 +2072,7 @@ __device__ __forceinline__ void pass_body(
             // straight-line cases keep the register array in place
             const C* m1 = matc + cur.mat + (TWO ? 4 : 0);
             const C* m2 = matc + cur.mat + (TWO ? 16 : 0);
+            const C* sp = matc + cur.mat + (TWO ? 10 : 8);
             switch (cur.opc) {
               case 0: op1<0, false, TWO>(v, w, m1); break;
               case 1: op1<1, false, TWO>(v, w, m1); break;
@@ -2043,6 +2102,14 @@ __device__ __forceinline__ void pass_body(
               case 29: op1x<1, TWO>(v, w, m1); break;
               case 30: op1x<2, TWO>(v, w, m1); break;
               case 31: op1x<3, TWO>(v, w, m1); break;
+              case 32: op1s<0, false, TWO>(v, w, sp); break;
+              case 33: op1s<1, false, TWO>(v, w, sp); break;
+              case 34: op1s<2, false, TWO>(v, w, sp); break;
+              case 35: op1s<3, false, TWO>(v, w, sp); break;
+              case 36: op1s<0, true, TWO>(v, w, sp); break;
+              case 37: op1s<1, true, TWO>(v, w, sp); break;
+              case 38: op1s<2, true, TWO>(v, w, sp); break;
+              case 39: op1s<3, true, TWO>(v, w, sp); break;
               case 40: if constexpr (!TWO) oplane<0, 0, TWO>(v, w, m1, tid); break;
               case 41: if constexpr (!TWO) oplane<1, 0, TWO>(v, w, m1, tid); break;
               case 42: if constexpr (!TWO) oplane<2, 0, TWO>(v, w, m1, tid); break;
@@ -2061,6 +2128,7 @@ __device__ __forceinline__ void pass_body(
               case 55: if constexpr (!TWO) oplane<3, 3, TWO>(v, w, m1, tid); break;
               default: break;
             }
+            if (cur.opc >= 32 && cur.opc < 40) neg = neg != (sp[1].x < 0);
             continue;
           }
           // controlled ops (register-slot or in-tile controls): predicated per
@@ -2081,6 +2149,17 @@ __device__ __forceinline__ void pass_body(
             const C* mp = matc + cur.mat + (TWO ? 16 : 0);
             r2_any(v, k0, k1, mp, creg);
             if (TWO) r2_any(w, k0, k1, mp, creg);
+          }
+        }
+        if (si == nst - 1 && neg) {  // the tile's shear-form rotations left it negated
+#pragma unroll
+          for (int e = 0; e < NE; ++e) {
+            v[e].x = -v[e].x;
+            v[e].y = -v[e].y;
+            if (TWO) {
+              w[e].x = -w[e].x;
+              w[e].y = -w[e].y;
+            }
           }
         }
         // (no barrier before the scatter in the two-state pass: every thread
@@ -2288,7 +2367,10 @@ __global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ ps
   }
 }
 
-// matrices of a rotation exp(-i theta P/2) (slot 0..3) and of its inverse (4..7)
+// matrices of a rotation exp(-i theta P/2) (slot 0..3) and of its inverse
+// (4..7); then, for X and Y, the three-shear form of the plane rotation by
+// phi = theta/2 (slots 8..9, inverse 10..11): phi = phi' + k pi with
+// |phi'| <= pi/2, slot 8/10 = (tan(phi'/2), sin(phi')), slot 9/11 = ((-1)^k, 0)
 template <typename C>
 __device__ __forceinline__ void rot_fill(C* m, int pauli, double theta) {
   double s, c;
@@ -2303,6 +2385,15 @@ __device__ __forceinline__ void rot_fill(C* m, int pauli, double theta) {
     } else {
       o[0] = mk<C>(c, -si); o[1] = mk<C>(0, 0); o[2] = mk<C>(0, 0); o[3] = mk<C>(c, si);
     }
+  }
+  if (pauli == 1 || pauli == 2) {
+    const double phi = 0.5 * theta, k = rint(phi * 0.3183098861837907);
+    const double r = phi - 3.141592653589793 * k;
+    const double t = tan(0.5 * r), sr = sin(r), sg = fmod(k, 2.0) == 0.0 ? 1.0 : -1.0;
+    m[8] = mk<C>(t, sr);
+    m[9] = mk<C>(sg, 0);
+    m[10] = mk<C>(-t, -sr);
+    m[11] = mk<C>(sg, 0);
   }
 }
 
@@ -2438,20 +2529,7 @@ __global__ void k_rot_mats(const TileOp* __restrict__ ops, int nops, const doubl
   if (i >= nops) return;
   const TileOp op = ops[i];
   if (op.kind != OP_ROT || op.mat < 0) return;
-  double s, c;
-  sincos(0.5 * op.sign * params[op.pidx], &s, &c);
-  C* m = matc + op.mat;
-  for (int inv = 0; inv < 2; ++inv) {
-    const double si = inv ? -s : s;
-    C* o = m + 4 * inv;
-    if (op.pauli == 1) {
-      o[0] = mk<C>(c, 0); o[1] = mk<C>(0, -si); o[2] = mk<C>(0, -si); o[3] = mk<C>(c, 0);
-    } else if (op.pauli == 2) {
-      o[0] = mk<C>(c, 0); o[1] = mk<C>(-si, 0); o[2] = mk<C>(si, 0); o[3] = mk<C>(c, 0);
-    } else {
-      o[0] = mk<C>(c, -si); o[1] = mk<C>(0, 0); o[2] = mk<C>(0, 0); o[3] = mk<C>(c, si);
-    }
-  }
+  rot_fill(matc + op.mat, op.pauli, op.sign * params[op.pidx]);
 }
 
 hipError_t set_lds_fn(void* fn, size_t lds) {

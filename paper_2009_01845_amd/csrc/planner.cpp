@@ -843,8 +843,9 @@ void close_pass(Plan& plan, const HostCircuit& C, int m, int L, std::set<int>& h
           op.gslot = plan.ngrad_slots++;
           op.aux = ngrad++;
         }
-        op.mat = (int)plan.matpool.size();  // forward and inverse 2x2, written per run
-        plan.matpool.insert(plan.matpool.end(), 8, cd(0, 0));
+        // forward and inverse 2x2, then their three-shear parameters, written per run
+        op.mat = (int)plan.matpool.size();
+        plan.matpool.insert(plan.matpool.end(), 12, cd(0, 0));
       } else {
         const int dim = 1 << bg.k;
         op.mat = (int)plan.matpool.size();
@@ -939,6 +940,8 @@ std::vector<StagedOp> staged_records(const std::vector<TileOp>& ops, const std::
     if (one && (op.flags & 32u)) {  // lane ops
       const int form = (op.flags & 16u) ? 2 : (op.flags & 8u) ? 3 : (op.flags & 1u) ? 1 : 0;
       r.opc = 40 + 4 * form + op.b[0];
+    } else if (op.kind == OP_ROT && (op.pauli == 1 || op.pauli == 2)) {  // X / Y rotation: three shears
+      r.opc = (op.pauli == 1 ? 36 : 32) + op.b[0];
     } else if (one) {
       r.opc = ((op.flags & 16u) ? 24 : (op.flags & 8u) ? 28 : (op.flags & 1u) ? 4 : 0) + op.b[0];
     } else if (op.kind == OP_DENSE2) {
