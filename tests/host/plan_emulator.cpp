@@ -6,7 +6,7 @@
 // Both the one-state form of each pass and its two-state (adjoint) form are
 // checked.  Exit status 0 when both agree to 1e-9.
 //
-//   plan_emulator <n> <tile_bits> <seed> <mode> [lane_ops]
+//   plan_emulator <n> <tile_bits> <seed> <mode> [lane_ops] [complex128]
 //   mode 0: random 1-/2-qubit gates with 0..2 controls (dense and diagonal)
 //   mode 1: layers of X/Y/Z rotations on every qubit and a CZ ring
 //   mode 2: QFT with its closing SWAPs
@@ -149,7 +149,8 @@ int main(int argc, char** argv) {
   TuneOpts o;
   o.tile_bits = tile_bits;
   o.lane_ops = argc > 5 ? atoi(argv[5]) != 0 : true;
-  const Plan p = plan_circuit(C, o, false);
+  const bool dbl = argc > 6 && atoi(argv[6]) != 0;  // plan for complex128
+  const Plan p = plan_circuit(C, o, dbl);
 
   std::vector<Z> psi0(1ull << n);
   for (auto& v : psi0) v = Z(N01(rng), N01(rng));

@@ -24,13 +24,14 @@ def emulator(tmp_path_factory):
     return out
 
 
+@pytest.mark.parametrize("dbl", [0, 1])
 @pytest.mark.parametrize("lanes", [0, 1])
 @pytest.mark.parametrize("n,tile_bits,seed,mode", [
     (15, 0, s, 0) for s in range(1, 9)] + [(14, 12, s, 0) for s in range(1, 9)] + [(15, 13, 2, 0)] +
     [(n, 12, 5, 1) for n in (12, 13, 14, 15, 16)] + [(n, 12, 5, 2) for n in (12, 13, 14, 16)])
-def test_planned_ops_replay_the_circuit(emulator, n, tile_bits, seed, mode, lanes):
-    r = subprocess.run([emulator, str(n), str(tile_bits), str(seed), str(mode), str(lanes)], capture_output=True,
-                       text=True)
+def test_planned_ops_replay_the_circuit(emulator, n, tile_bits, seed, mode, lanes, dbl):
+    r = subprocess.run([emulator, str(n), str(tile_bits), str(seed), str(mode), str(lanes), str(dbl)],
+                       capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
 
 
