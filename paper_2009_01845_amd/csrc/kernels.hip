@@ -1740,7 +1740,7 @@ __device__ __forceinline__ void pass_body(
     for (int i = 0; i < H; ++i) tm |= 1ull << g.hbits[i];
     for (int q = 0; q < n; ++q) {
       if ((tm >> q) & 1) continue;
-      if (idx >= gbits && idx - gbits < kMaxKBits) kpos[idx - gbits] = q;
+      if (idx < kb && idx < kMaxKBits) kpos[idx] = q;
       ++idx;
     }
   }
@@ -1755,7 +1755,11 @@ __device__ __forceinline__ void pass_body(
   auto pos = [&](int b) { return b < L ? b : hb[b - L]; };
   // every thread moves NLD 16-byte vectors per tile and state
   auto tbase = [&](int64_t tt) {
-    uint64_t b = (uint64_t)tt << L;
+    // the grid bits of the tile index (which differ between workgroups running
+    // at the same time) fill the highest non-tile index positions, the
+    // per-workgroup walk the lowest ones
+    const uint64_t tr = ((uint64_t)tt >> gbits) | (((uint64_t)tt & ((1ull << gbits) - 1ull)) << kb);
+    uint64_t b = tr << L;
     for (int i = 0; i < H; ++i) b = insert_zero64(b, hb[i]);
     return b;
   };

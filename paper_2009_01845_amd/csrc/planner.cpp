@@ -650,7 +650,8 @@ void stage_ops(Plan& plan, PassGeom& g, std::vector<TileOp>& pops, bool lanes, b
         // per thread group jg (register bits zero): theta_T(jg) and, for each
         // register slot k, mu_k + sum_{a in jg} lam_{a,k}
         // a workgroup visits tiles t = t0 + kk * G (G = 2^gb workgroups); the
-        // tile-index bits above gb ("k bits") sit at global positions kp[j]
+        // staged kernel places the gb grid bits of t at the highest non-tile
+        // index positions and the k bits (kk) at the lowest ones, kp[j]
         {
           const int ntb = n - g.m;
           const int gb = std::min(ntb, plan.grid_bits);
@@ -662,7 +663,7 @@ void stage_ops(Plan& plan, PassGeom& g, std::vector<TileOp>& pops, bool lanes, b
             bool tile = q < g.L;
             for (int h = 0; h < g.H; ++h) tile |= g.hbits[h] == q;
             if (tile) continue;
-            if (idx >= gb) kp.push_back(q);
+            if (idx < kb) kp.push_back(q);
             ++idx;
           }
           rec.kt_off = (int)plan.btab.size();
