@@ -150,6 +150,16 @@ __device__ __forceinline__ uint64_t tile_index(uint64_t x, const PassGeom& g) {
   }
   return y;
 }
+// Tiles walked by a grid-strided loop (t = block + k * grid): the low bits of t
+// differ between workgroups running at the same time.  Rotating them to the
+// top of the tile index spreads concurrent workgroups over the highest
+// non-tile index bits instead of neighbouring tiles (with a high bit in the
+// tile, neighbouring tiles are pairs of runs gigabytes apart, and the
+// streaming rate drops by up to 17%).  A bijection on [0, 2^tbits).
+__device__ __forceinline__ uint64_t spread_tile(uint64_t t, int tbits) {
+  const int s = tbits < kGridBits ? tbits : kGridBits;
+  return (t >> s) | ((t & ((1ull << s) - 1ull)) << (tbits - s));
+}
 __device__ __forceinline__ uint64_t tile_base(uint64_t t, const PassGeom& g) {
   uint64_t b = t << g.L;
   for (int i = 0; i < g.H; ++i) b = insert_zero64(b, g.hbits[i]);
@@ -324,7 +334,7 @@ __global__ __launch_bounds__(256) void k_tile(typename CT<R>::C* __restrict__ ps
   const uint32_t lomask = (1u << L) - 1u;
 
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint64_t base = tile_base((uint64_t)t, g);
+    const uint64_t base = tile_base(spread_tile((uint64_t)t, g.n - g.m), g);
     for (int e = tid * VW; e < M; e += kThreads * VW) {
       const uint64_t a = base | hoff[e >> L] | (uint64_t)(e & lomask);
       *reinterpret_cast<VT*>(t1 + e) = *reinterpret_cast<const VT*>(psi + a);
@@ -810,7 +820,7 @@ __global__ __launch_bounds__(256) void k_pauli_tile(const typename CT<R>::C* __r
   constexpr bool PAIR = WRITE && sizeof(R) == 4;
   auto yof = [&](int e) { return PAIR ? ((e >> 1) * kThreads + tid) * 2 + (e & 1) : tid + e * kThreads; };
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    uint64_t base = (uint64_t)t << L;
+    uint64_t base = spread_tile((uint64_t)t, ps.n - m) << L;
     for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
     auto gaddr = [&](int y) { return base | hoff[y >> L] | (uint64_t)(y & lomask); };
     if (sizeof(R) == 4 && M == EPT * kThreads) {
@@ -2319,7 +2329,7 @@ __global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ ps
   const uint32_t lomask = (1u << L) - 1u;
   (void)m;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    uint64_t base = (uint64_t)t << L;
+    uint64_t base = spread_tile((uint64_t)t, g.n - g.m) << L;
     for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
     VT buf[NLD];
 #pragma unroll
