@@ -2544,11 +2544,11 @@ __global__ void k_phase_tabs(const PhaseRec* __restrict__ phases, const double* 
   }
 }
 
-// forward and inverse rotation matrices, exp(-i theta P / 2) and its inverse
+// forward and inverse rotation matrices, exp(-i theta P / 2) and its inverse,
+// with their three-shear parameters (rot_fill)
 template <typename R>
 __global__ void k_rot_mats(const TileOp* __restrict__ ops, int nops, const double* __restrict__ params,
                            typename CT<R>::C* __restrict__ matc) {
-  using C = typename CT<R>::C;
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= nops) return;
   const TileOp op = ops[i];
