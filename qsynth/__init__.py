@@ -134,6 +134,19 @@ def ry_czring_layers(n: int, params: np.ndarray):
     return out
 
 
+def ry_then_phases(n: int, theta: np.ndarray, seed: int):
+    """RY(theta_q) on every qubit (parameter index q), then controlled phase
+    gates U1(phi) on the ring (q, q+1 mod n) and on the pairs (q, q + n/2),
+    phi ~ U[0.1, 3.0] from ``seed`` (never a multiple of pi)."""
+    rng = np.random.default_rng(seed)
+    out = [gate("RY", (q,), theta=theta[q], pidx=q) for q in range(n)]
+    pairs = [(q, (q + 1) % n) for q in range(n)] + [(q, q + n // 2) for q in range(n // 2)]
+    for a, b in pairs:
+        if a != b:
+            out.append(gate("U1", (max(a, b),), (min(a, b),), theta=float(rng.uniform(0.1, 3.0))))
+    return out
+
+
 def random_layers(n: int, depth: int, seed: int):
     """Depth x (Haar 1-qubit gate on every qubit, then CZ on a seeded random
     perfect matching of the qubits)."""

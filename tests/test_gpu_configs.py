@@ -178,6 +178,30 @@ def test_adjoint_full_size_product_layers_closed_form(api, n, dt):
     _free()
 
 
+@pytest.mark.parametrize("n,dt", [(24, "c128"), (24, "c64"), (27, "c64")])
+def test_adjoint_general_phases_with_tile_index_k_bits_closed_form(api, n, dt):
+    # RY on every qubit, then controlled phases (angles not multiples of pi)
+    # on the ring and on pairs n/2 apart, H = sum Z_i: the phases commute with
+    # H, so E = sum cos t_q and dE/dt_q = -sin t_q (pinned through the oracle
+    # in test_oracle_pins.py).  At 24 and more qubits the two-state passes
+    # walk tiles whose index has bits above the grid, so this checks the
+    # general-phase tables of the adjoint at those sizes; a phase misplaced on
+    # a rotation's target bit would show in its gradient
+    banner("adjoint closed form, general phases", n, dt)
+    th = np.random.default_rng(n + 7).uniform(0, 2 * np.pi, n)
+    spec = qsynth.ry_then_phases(n, th, seed=n)
+    circ = api.Circuit.from_spec(n, spec)
+    H = api.Observable.pauli_sum(n, qsynth.z_sum(n))
+    psi, lam = api.State(n, dt), api.State(n, dt)
+    circ.run(psi, th)
+    E, g = api.adjoint(circ.h, th, H.h, psi.h, lam.h, circ.nparams)
+    err = float(np.max(np.abs(g + np.sin(th))))
+    banner("general phases", n, dt, "|dE|", abs(E - float(np.sum(np.cos(th)))), "max|dgrad|", err)
+    assert abs(E - float(np.sum(np.cos(th)))) < GTOL[dt] and err < GTOL[dt]
+    del psi, lam
+    _free()
+
+
 # ---------------------------------------------------------------------------
 # batch workload: 512 instances (n ~ U{8..18}, depth ~ U{4..12}); every
 # instance with n >= 16 against its oracle adjoint

@@ -350,6 +350,24 @@ def test_boundary_distance_on_a_dyadic_cdf():
     assert np.isclose(d2[0], 0.35)
 
 
+# ------------------------- diagonal gates after the rotations: sum Z unchanged
+@pytest.mark.parametrize("n", [4, 6])
+def test_phases_after_ry_layer_leave_z_sum_closed_form(n):
+    # controlled phases are diagonal: they commute with every Z_i, so after
+    # RY(t_q)|0> they change neither <sum Z_i> = sum cos t_q nor its gradient
+    # -sin t_q, whatever their angles
+    th = np.random.default_rng(n + 7).uniform(0, 2 * np.pi, n)
+    spec = qsynth.ry_then_phases(n, th, seed=n)
+    assert sum(g.name == "U1" for g in spec) >= n
+    E, g = gradients.adjoint(n, spec, th, qsynth.z_sum(n))
+    assert abs(E - float(np.sum(np.cos(th)))) < 1e-13
+    assert np.max(np.abs(g + np.sin(th))) < 1e-13
+    # the phases do act on the state
+    psi = circuits.run(n, spec, None, th)
+    psi_ry = circuits.run(n, qsynth.ry_layers(n, th), None, th)
+    assert np.max(np.abs(psi - psi_ry)) > 1e-3
+
+
 # ------------------------------------------- product-state energy closed form
 @pytest.mark.parametrize("n", [3, 6])
 def test_ry_layer_ring_energy_closed_form(n):
