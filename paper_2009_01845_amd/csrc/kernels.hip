@@ -2450,8 +2450,12 @@ __global__ __launch_bounds__(256) void k_batch_init(const BatchArgs a, const Bat
   for (int64_t x = x0 + threadIdx.x; x < x1; x += kThreads) psi[x] = mk<C>(x == 0 ? 1.0 : 0.0, 0.0);
 }
 
+// complex64 forward batch passes are held to four waves per SIMD (166
+// registers otherwise; an 84-byte scratch spill): the 512-instance replay
+// 8.51 against 8.81 ms, energies only 2.90 against 3.16 ms.  Bounding the
+// two-state batch pass as well spilled more and was slower.
 template <typename R, bool TWO, int NLD, bool CTRL>
-__global__ __launch_bounds__(256) void k_batch_pass(const BatchArgs a, const BatchItem* __restrict__ items) {
+__global__ __launch_bounds__(256, (sizeof(R) == 4 && !TWO ? 4 : 1)) void k_batch_pass(const BatchArgs a, const BatchItem* __restrict__ items) {
   using C = typename CT<R>::C;
   extern __shared__ __align__(16) char smem[];
   __shared__ PassSmem sm;
