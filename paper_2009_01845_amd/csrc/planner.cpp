@@ -29,6 +29,7 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kPi = 3.141592653589793238462643383279;
 constexpr int kRolloutMaxGates = 6000;  // longer gate lists skip the rollout schedule
 constexpr int kRolloutMaxFront = 48;    // first choices tried per pass by the rollout
+constexpr int kMaxHighBits = 7;         // a tile holds at most 2^7 rows
 
 bool is_diag(const std::vector<cd>& m, int dim) {
   for (int r = 0; r < dim; ++r)
@@ -144,7 +145,7 @@ void default_tile(int n, bool dbl, const TuneOpts& o, int* m, int* L) {
   if (mm > n) mm = n;
   if (ll > mm) ll = mm;
   if (mm < n && mm - ll < 5) ll = std::max(1, mm - 5);  // room for a 5-qubit gate
-  if (mm - ll > 7) ll = mm - 7;                          // at most 2^7 rows per tile
+  if (mm - ll > kMaxHighBits) ll = mm - kMaxHighBits;    // at most 2^7 rows per tile
   if (ll > 8) ll = 8;
   *m = mm;
   *L = ll;
@@ -1083,7 +1084,9 @@ void add_perm_pass(Plan& plan, int n, int L, bool dbl, const std::vector<int>& t
 
 }  // namespace
 
-Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
+namespace {
+
+Plan plan_tiles(const HostCircuit& C, const TuneOpts& opts, bool dbl, int m, int L) {
   const int n = C.n;
   Plan proto;
   proto.n = n;
@@ -1093,8 +1096,6 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
   proto.grid_bits = opts.grid_bits;
   proto.force_stage = opts.force_stage;
   proto.lane_ops = opts.lane_ops;
-  int m, L;
-  default_tile(n, dbl, opts, &m, &L);
   const int Hmax = m - L;
 
   // 0. optional fusion of consecutive fixed gates into <= fuse_k-qubit blocks
@@ -1446,6 +1447,24 @@ Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
         plan.schedule = mode;
       }
     }
+  return plan;
+}
+
+}  // namespace
+
+// With the row length left open (low_bits 0), rows one bit shorter than the
+// default free a tile bit for the high positions.  A pass over such rows
+// costs a few percent more (256 instead of 512 contiguous bytes for
+// complex64), so that plan is kept only when it needs fewer passes: a ring of
+// RY layers and CZ gates on 30 qubits takes 11 passes instead of 13.
+Plan plan_circuit(const HostCircuit& C, const TuneOpts& opts, bool dbl) {
+  int m, L;
+  default_tile(C.n, dbl, opts, &m, &L);
+  Plan plan = plan_tiles(C, opts, dbl, m, L);
+  if (opts.low_bits == 0 && L > 1 && m - L < kMaxHighBits && m < C.n && plan.passes.size() > 1) {
+    Plan alt = plan_tiles(C, opts, dbl, m, L - 1);
+    if (alt.passes.size() < plan.passes.size()) plan = std::move(alt);
+  }
   return plan;
 }
 

@@ -207,7 +207,7 @@ def test_schedule_query_and_rollout_planning_time(api):
     import time
     n = 20
     _, spec, _, _ = qsynth.gradient_20q(seed=0, n=n, layers=12)
-    c = api.Circuit.from_spec(n, spec)
+    c = api.Circuit.from_spec(n, spec, low_bits=6)
     assert c.schedule() == 2          # the one-step rollout gives the shortest plan here
     rng = np.random.default_rng(5)
     brick = [qsynth.gate("MAT", (q, q + 1), mat=qsynth.haar_unitary(4, rng))
@@ -227,3 +227,17 @@ def test_schedule_query_and_rollout_planning_time(api):
     c = api.Circuit.from_spec(n, spec)
     assert time.perf_counter() - t < 60.0
     assert c.info()[0] == 3600
+
+
+def test_default_row_length_follows_pass_count(api):
+    # with low_bits left open the planner also plans rows one bit shorter and
+    # keeps that plan only when it has fewer passes
+    _, spec, _, _ = qsynth.gradient_20q(seed=0, n=30, layers=10)
+    counts = {lb: api.Circuit.from_spec(30, spec, low_bits=lb).info()[1] for lb in (0, 5, 6)}
+    assert counts == {0: 11, 5: 11, 6: 13}
+    _, spec, _, _ = qsynth.gradient_20q(seed=0, n=20, layers=12)
+    counts = {lb: api.Circuit.from_spec(20, spec, low_bits=lb).info()[1] for lb in (0, 5, 6)}
+    assert counts == {0: 7, 5: 7, 6: 9}
+    # the QFT needs five passes either way
+    counts = {lb: api.Circuit.from_spec(30, qsynth.qft(30), low_bits=lb).info()[1] for lb in (0, 6)}
+    assert counts == {0: 5, 6: 5}
