@@ -1062,6 +1062,10 @@ void add_perm_pass(Plan& plan, int n, int L, bool dbl, const std::vector<int>& t
   bool ident = true;
   for (int a = 0; a < n; ++a) ident &= tau[a] == a;
   if (ident) return;
+  // the tile holds the low bits and their images: at most 2L bits, and the
+  // permutation kernel takes tiles of at most 2^12 (complex64) or 2^11
+  // (complex128) amplitudes
+  L = std::min(L, dbl ? 5 : 6);
   Pass ps;
   ps.kind = PASS_PERM;
   ps.sigma = tau;

@@ -178,6 +178,19 @@ def test_qft_random_state_vs_fft(api, dt):
     assert maxabs(st.download(), ocirc.qft_via_fft(oracle_input(psi0, dt))) < TOL[dt]
 
 
+@pytest.mark.parametrize("dt,low_bits", [("c64", 7), ("c128", 6), ("c128", 7)])
+def test_qft_long_rows_vs_fft(api, dt, low_bits):
+    # rows longer than the default: the closing bit reversal still fits the
+    # permutation kernel's tile
+    n = 16
+    banner("qft long rows", dt, n, low_bits)
+    psi0 = qsynth.random_state(n, 4)
+    c = api.Circuit.from_spec(n, qsynth.qft(n), low_bits=low_bits)
+    st = gpu_state(api, n, dt, psi0)
+    c.run(st)
+    assert maxabs(st.download(), ocirc.qft_via_fft(oracle_input(psi0, dt))) < TOL[dt]
+
+
 @pytest.mark.parametrize("dt,n", [("c64", 28), ("c128", 28), ("c64", 30)])
 def test_qft_basis_closed_form_large(api, dt, n):
     banner("qft basis large", dt, n)
