@@ -600,9 +600,12 @@ def main():
     per = {k: v / args.steps for k, v in comp.items()}
     fwd_ms = per["var_fwd"] + per["energy"]
     mf_n, mf_ms = fam["mfma"]
-    # the six blocks: 3 of k = 5 and 3 of k = 4, 8 * 2^k * 2^n real flops each
+    # the six blocks: 3 of k = 5 and 3 of k = 4, 8 * 2^k * 2^n real flops each,
+    # in as many matrix-core launches a step as the plan has such passes
+    # (blocks on disjoint bits that fit one tile share one)
     mf_flops = 3 * 8 * 32 * (1 << n) + 3 * 8 * 16 * (1 << n)
-    mf_tflops = mf_flops / (mf_ms / max(mf_n, 1) * 6 / 1e3) / 1e12 if mf_n else None
+    mf_per_step = sum(1 for k, _, _ in blocks.passes() if k == 4)
+    mf_tflops = mf_flops / (mf_ms / max(mf_n, 1) * mf_per_step / 1e3) / 1e12 if mf_n else None
     mf_gbs = bytes_pass / (mf_ms / max(mf_n, 1) / 1e3) / 1e9 if mf_n else None
     passes_total = qft.info()[1] + var.info()[1]
 
@@ -634,7 +637,7 @@ def main():
         "adjoint_over_forward": per["adjoint"] / fwd_ms,
         "mfma_blocks": {"tflops": mf_tflops, "peak_tflops": FP32_PEAK_TFLOPS,
                         "util": mf_tflops / FP32_PEAK_TFLOPS if mf_tflops else None,
-                        "hbm_gbps": mf_gbs, "launches": mf_n},
+                        "hbm_gbps": mf_gbs, "launches": mf_n, "launches_per_step": mf_per_step},
         "components_ms": per,
         "family_avg_ms": {k: (ms / c if c else None) for k, (c, ms) in fam.items()},
         "kernels_sha256_16": kernel_source_hash(),

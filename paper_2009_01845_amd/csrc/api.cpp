@@ -386,10 +386,16 @@ void run_passes(const DevPlanBuf& dp, const Plan& plan, bool dbl, void* psi, voi
       if (lam) hipck(launch_perm_pass(dbl, lam, ps.geom, ps.sigma.data(), s), "perm pass");
     } else if (ps.kind == PASS_MFMA) {
       ProfScope pr(3, s);
+      // a fused pass holds two blocks on disjoint bits; they commute, so the
+      // adjoint un-applies both in the same launch
       const TileOp& op = ps.ops[0];
-      const double* m = dp.view.mat + 2 * (op.mat + (lam ? (1 << (2 * op.k)) : 0));
-      hipck(launch_mfma_pass(dbl, psi, ps.geom, op.b, op.k, m, s), "mfma pass");
-      if (lam) hipck(launch_mfma_pass(dbl, lam, ps.geom, op.b, op.k, m, s), "mfma pass");
+      const TileOp* op2 = ps.ops.size() > 1 ? &ps.ops[1] : nullptr;
+      const int inv = lam ? (1 << (2 * op.k)) : 0;
+      const double* m = dp.view.mat + 2 * (op.mat + inv);
+      const double* m2 = op2 ? dp.view.mat + 2 * (op2->mat + inv) : nullptr;
+      const int* tl2 = op2 ? op2->b : nullptr;
+      hipck(launch_mfma_pass(dbl, psi, ps.geom, op.b, op.k, m, tl2, m2, s), "mfma pass");
+      if (lam) hipck(launch_mfma_pass(dbl, lam, ps.geom, op.b, op.k, m, tl2, m2, s), "mfma pass");
     } else {
       ProfScope pr(lam ? 7 : 0, s);
       hipck(launch_tile_pass(dbl, psi, lam, lam ? dp.geoms_adj[i] : dp.geoms[i], dp.view, params, scales, gpart, s),

@@ -135,10 +135,12 @@ hipError_t launch_rot_mats(bool dbl, const DevPlan& dp, const double* params, hi
 hipError_t launch_phase_tabs(bool dbl, const DevPlan& dp, const double* scales, hipStream_t s);
 hipError_t launch_perm_pass(bool dbl, void* psi, const PassGeom& g, const int* tau, hipStream_t s);
 // Dense k-qubit block (k = 4, 5) with matrix-core instructions; the tile is the
-// targets plus the 7 lowest other bits (g.m == k + 7); tl[t] = tile-local
-// position of target t; mat = 2^k x 2^k complex128 (device).
+// targets plus 7 other bits (g.m == k + 7), the low bits first; tl[t] =
+// tile-local position of target t; mat = 2^k x 2^k complex128 (device).  With
+// tl2 and mat2 (else both null) a second k-qubit block on other tile bits is
+// applied to the same tile after the first (k = 4 only for complex128).
 hipError_t launch_mfma_pass(bool dbl, void* psi, const PassGeom& g, const int* tl, int k, const double* mat,
-                            hipStream_t s);
+                            const int* tl2, const double* mat2, hipStream_t s);
 
 hipError_t launch_set_basis(bool dbl, void* psi, int n, uint64_t x, hipStream_t s);
 hipError_t launch_set_plus(bool dbl, void* psi, int n, hipStream_t s);

@@ -2261,9 +2261,13 @@ __global__ __launch_bounds__(256, (Tile2Waves<R, TWO, CTRL, NLD>::value)) void k
 // real product [Yr; Yi] = GR [Xr; Xi].  v_mfma_*_16x16x4: A is 16x4 (lane l
 // holds row l%16, column l/16), B is 4x16 (row l/16, column l%16), D is 16x16
 // with column l%16 and row 4*(l/16)+v (f32) or 4*v+l/16 (f64) in element v.
+// A fused pass applies a second k-qubit block on other bits of the same tile:
+// its targets lie among the first block's columns and the other way round, so
+// the tile is taken from HBM once for both.
 // ----------------------------------------------------------------------------
 struct MfmaArgs {
-  int tl[5];  // tile-local position of target t (t = 0 is the matrix MSB)
+  int tl[5];   // tile-local position of target t (t = 0 is the matrix MSB)
+  int tl2[5];  // fused passes: the same for the second block
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -2287,26 +2291,91 @@ template <> struct MfmaT<double> {
   static __device__ __forceinline__ int out_row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
 
-template <typename R, int K, int NLD>
+// row and column offsets of a block with targets tl inside the tile
+template <int K, int NCOL>
+__device__ __forceinline__ void mfma_offsets(const int (&tl)[5], uint32_t* rowoff, uint32_t* coloff, int tid) {
+  uint32_t tmask = 0;
+#pragma unroll
+  for (int t = 0; t < K; ++t) tmask |= 1u << tl[t];
+  for (int r = tid; r < (1 << K); r += kThreads) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      if ((r >> (K - 1 - t)) & 1) o |= 1u << tl[t];
+    rowoff[r] = o;
+  }
+  for (int c = tid; c < NCOL; c += kThreads) coloff[c] = insert_zeros((uint32_t)c, tmask);
+}
+
+// A fragments of the realified gate, resident for the whole launch
+template <typename R, int K>
+__device__ __forceinline__ void mfma_frags(const double* __restrict__ mat, R (&a)[2 * (1 << K) / 16][2 * (1 << K) / 4],
+                                           int lane) {
+  constexpr int D = 1 << K;
+#pragma unroll
+  for (int rb = 0; rb < 2 * D / 16; ++rb)
+#pragma unroll
+    for (int ks = 0; ks < 2 * D / 4; ++ks) {
+      const int i = 16 * rb + (lane & 15), j = 4 * ks + (lane >> 4);
+      const int gi = i & (D - 1), gj = j & (D - 1);
+      const double re = mat[2 * (gi * D + gj)], im = mat[2 * (gi * D + gj) + 1];
+      a[rb][ks] = (R)((i < D) == (j < D) ? re : (i < D ? -im : im));
+    }
+}
+
+// one block on the tile in LDS: each wave takes 16 columns at a time, reads
+// their 2^K values, and writes the products back to the same entries
+template <typename R, int K>
+__device__ __forceinline__ void mfma_apply(typename CT<R>::C* tile, const uint32_t* rowoff, const uint32_t* coloff,
+                                           const R (&a)[2 * (1 << K) / 16][2 * (1 << K) / 4], int lane, int wave) {
+  using C = typename CT<R>::C;
+  using Acc = typename MfmaT<R>::Acc;
+  constexpr int D = 1 << K, RB = 2 * D / 16, KS = 2 * D / 4, NCOL = 128;
+  for (int cb = wave; cb < NCOL / 16; cb += (int)(kThreads >> 6)) {
+    const uint32_t co = coloff[16 * cb + (lane & 15)];
+    Acc acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int row = 4 * ks + (lane >> 4);  // realified row of X
+      const C x = tile[swz<R>(rowoff[row & (D - 1)] | co)];
+      const R bval = row < D ? x.x : x.y;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = MfmaT<R>::mma(a[rb][ks], bval, acc[rb]);
+    }
+    // output row 16*rb + 4*(lane/16) + v: real parts in the first RB/2 blocks,
+    // imaginary parts of the same rows RB/2 blocks later
+#pragma unroll
+    for (int rb = 0; rb < RB / 2; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * rb + MfmaT<R>::out_row(lane, v);
+        tile[swz<R>(rowoff[row] | co)] = mk<C>(acc[rb][v], acc[rb + RB / 2][v]);
+      }
+  }
+}
+
+template <typename R, int K, int NLD, bool TWO_M>
 __global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ psi, const PassGeom g,
-                                              const MfmaArgs ma, const double* __restrict__ mat, int64_t ntiles) {
+                                              const MfmaArgs ma, const double* __restrict__ mat,
+                                              const double* __restrict__ mat2, int64_t ntiles) {
   using C = typename CT<R>::C;
   using VT = typename CT<R>::V;
-  using Acc = typename MfmaT<R>::Acc;
   constexpr int VW = CT<R>::VW;
   constexpr int D = 1 << K;      // complex dimension
-  constexpr int DR = 2 * D;      // realified dimension
-  constexpr int RB = DR / 16;    // 16-row blocks of the output
-  constexpr int KS = DR / 4;     // 4-deep steps of the contraction
+  constexpr int RB = 2 * D / 16;  // 16-row blocks of the realified output
+  constexpr int KS = 2 * D / 4;   // 4-deep steps of the contraction
   constexpr int NCOL = 128;      // columns per tile
+  constexpr int NB = TWO_M ? 2 : 1;
   extern __shared__ __align__(16) char smem[];
   C* tile = reinterpret_cast<C*>(smem);
-  __shared__ uint32_t rowoff[D];
-  __shared__ uint32_t coloff[NCOL];
+  __shared__ uint32_t rowoff[NB][D];
+  __shared__ uint32_t coloff[NB][NCOL];
   __shared__ uint64_t hoff[128];
   __shared__ int hb[kMaxTileBits];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int L = g.L, H = g.H, m = g.m;
+  const int L = g.L, H = g.H;
   if (tid < kMaxTileBits) hb[tid] = g.hbits[tid];
   __syncthreads();
   for (int hc = tid; hc < (1 << H); hc += kThreads) {
@@ -2315,31 +2384,13 @@ __global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ ps
       if ((hc >> i) & 1) off |= 1ull << hb[i];
     hoff[hc] = off;
   }
-  uint32_t tmask = 0;
-#pragma unroll
-  for (int t = 0; t < K; ++t) tmask |= 1u << ma.tl[t];
-  for (int r = tid; r < D; r += kThreads) {
-    uint32_t o = 0;
-#pragma unroll
-    for (int t = 0; t < K; ++t)
-      if ((r >> (K - 1 - t)) & 1) o |= 1u << ma.tl[t];
-    rowoff[r] = o;
-  }
-  for (int c = tid; c < NCOL; c += kThreads) coloff[c] = insert_zeros((uint32_t)c, tmask);
-  // A fragments of the realified gate, resident for the whole launch
-  R a[RB][KS];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int i = 16 * rb + (lane & 15), j = 4 * ks + (lane >> 4);
-      const int gi = i & (D - 1), gj = j & (D - 1);
-      const double re = mat[2 * (gi * D + gj)], im = mat[2 * (gi * D + gj) + 1];
-      a[rb][ks] = (R)((i < D) == (j < D) ? re : (i < D ? -im : im));
-    }
+  mfma_offsets<K, NCOL>(ma.tl, rowoff[0], coloff[0], tid);
+  if constexpr (TWO_M) mfma_offsets<K, NCOL>(ma.tl2, rowoff[NB - 1], coloff[NB - 1], tid);
+  R a[RB][KS], a2[TWO_M ? RB : 1][TWO_M ? KS : 1];
+  mfma_frags<R, K>(mat, a, lane);
+  if constexpr (TWO_M) mfma_frags<R, K>(mat2, a2, lane);
   __syncthreads();
   const uint32_t lomask = (1u << L) - 1u;
-  (void)m;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     uint64_t base = spread_tile((uint64_t)t, g.n - g.m) << L;
     for (int i = 0; i < H; ++i) base = insert_zero64(base, hb[i]);
@@ -2355,28 +2406,10 @@ __global__ __launch_bounds__(256) void k_mfma(typename CT<R>::C* __restrict__ ps
       *reinterpret_cast<VT*>(tile + swz<R>(e)) = buf[u];
     }
     __syncthreads();
-    for (int cb = wave; cb < NCOL / 16; cb += (int)(kThreads >> 6)) {
-      const uint32_t co = coloff[16 * cb + (lane & 15)];
-      Acc acc[RB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) acc[rb] = Acc{0, 0, 0, 0};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int row = 4 * ks + (lane >> 4);  // realified row of X
-        const C x = tile[swz<R>(rowoff[row & (D - 1)] | co)];
-        const R bval = row < D ? x.x : x.y;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[rb] = MfmaT<R>::mma(a[rb][ks], bval, acc[rb]);
-      }
-      // output row 16*rb + 4*(lane/16) + v: real parts in the first RB/2 blocks,
-      // imaginary parts of the same rows RB/2 blocks later
-#pragma unroll
-      for (int rb = 0; rb < RB / 2; ++rb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 16 * rb + MfmaT<R>::out_row(lane, v);
-          tile[swz<R>(rowoff[row] | co)] = mk<C>(acc[rb][v], acc[rb + RB / 2][v]);
-        }
+    mfma_apply<R, K>(tile, rowoff[0], coloff[0], a, lane, wave);
+    if constexpr (TWO_M) {
+      __syncthreads();
+      mfma_apply<R, K>(tile, rowoff[NB - 1], coloff[NB - 1], a2, lane, wave);
     }
     __syncthreads();
 #pragma unroll
@@ -2716,40 +2749,52 @@ hipError_t perm_launch(int nld, void* psi, const PassGeom& g, const PermArgs& pa
   }
 }
 
-template <typename R, int K>
-hipError_t mfma_launch_t(void* psi, const PassGeom& g, const MfmaArgs& ma, const double* mat, hipStream_t s) {
+template <typename R, int K, bool TWO_M>
+hipError_t mfma_launch_t(void* psi, const PassGeom& g, const MfmaArgs& ma, const double* mat, const double* mat2,
+                         hipStream_t s) {
   constexpr int NLD = (1 << (K + 7)) / (kThreads * CT<R>::VW);
   const int64_t nt = 1ll << (g.n - g.m);
   const int grid = (int)(nt < kGridMax ? nt : kGridMax);
   const size_t lds = (size_t(1) << g.m) * sizeof(typename CT<R>::C);
-  hipError_t e = set_lds_fn((void*)k_mfma<R, K, NLD>, lds);
+  hipError_t e = set_lds_fn((void*)k_mfma<R, K, NLD, TWO_M>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mfma<R, K, NLD>), dim3(grid), dim3(kThreads), lds, s, (typename CT<R>::C*)psi, g, ma, mat,
-                     nt);
+  hipLaunchKernelGGL((k_mfma<R, K, NLD, TWO_M>), dim3(grid), dim3(kThreads), lds, s, (typename CT<R>::C*)psi, g, ma,
+                     mat, mat2, nt);
   return hipGetLastError();
 }
 
 hipError_t launch_mfma_pass(bool dbl, void* psi, const PassGeom& g, const int* tl, int k, const double* mat,
-                            hipStream_t s) {
+                            const int* tl2, const double* mat2, hipStream_t s) {
   // tile = targets + 7 other bits: L may reach 12 when the targets are low bits
   if (k < 4 || k > 5 || g.m != k + 7 || g.m > g.n || g.n > kMaxQubits) return hipErrorInvalidValue;
   if (g.L < 7 || g.L > 12 || g.H < 0 || g.H > 5 || g.L + g.H != g.m) return hipErrorInvalidValue;
   for (int i = 0; i < g.H; ++i)
     if (g.hbits[i] < g.L || g.hbits[i] >= g.n || (i && g.hbits[i] <= g.hbits[i - 1])) return hipErrorInvalidValue;
+  const bool two = tl2 != nullptr;
+  if (two != (mat2 != nullptr)) return hipErrorInvalidValue;
+  if (two && dbl && k == 5) return hipErrorInvalidValue;  // two complex128 blocks of 32 do not fit the registers
   MfmaArgs ma;
+  for (int t = 0; t < 5; ++t) ma.tl[t] = ma.tl2[t] = 0;
   uint32_t seen = 0;
-  for (int t = 0; t < 5; ++t) ma.tl[t] = 0;
   for (int t = 0; t < k; ++t) {
     if (tl[t] < 0 || tl[t] >= g.m || ((seen >> tl[t]) & 1)) return hipErrorInvalidValue;
     seen |= 1u << tl[t];
     ma.tl[t] = tl[t];
   }
-  if (dbl) {
-    if (k == 4) return mfma_launch_t<double, 4>(psi, g, ma, mat, s);
-    return mfma_launch_t<double, 5>(psi, g, ma, mat, s);
+  for (int t = 0; two && t < k; ++t) {  // the second block's targets: other tile bits
+    if (tl2[t] < 0 || tl2[t] >= g.m || ((seen >> tl2[t]) & 1)) return hipErrorInvalidValue;
+    seen |= 1u << tl2[t];
+    ma.tl2[t] = tl2[t];
   }
-  if (k == 4) return mfma_launch_t<float, 4>(psi, g, ma, mat, s);
-  return mfma_launch_t<float, 5>(psi, g, ma, mat, s);
+  if (dbl) {
+    if (two) return mfma_launch_t<double, 4, true>(psi, g, ma, mat, mat2, s);
+    if (k == 4) return mfma_launch_t<double, 4, false>(psi, g, ma, mat, nullptr, s);
+    return mfma_launch_t<double, 5, false>(psi, g, ma, mat, nullptr, s);
+  }
+  if (k == 4) return two ? mfma_launch_t<float, 4, true>(psi, g, ma, mat, mat2, s)
+                         : mfma_launch_t<float, 4, false>(psi, g, ma, mat, nullptr, s);
+  return two ? mfma_launch_t<float, 5, true>(psi, g, ma, mat, mat2, s)
+             : mfma_launch_t<float, 5, false>(psi, g, ma, mat, nullptr, s);
 }
 
 hipError_t launch_batch_rot(bool dbl, const BatchArgs& a, hipStream_t s) {

@@ -1012,48 +1012,61 @@ std::vector<Gate> fuse_gates(const std::vector<Gate>& in, int K) {
 namespace {
 
 // A dense block on matrix cores: tile = targets + the 7 lowest other bits.
-void add_mfma_pass(Plan& plan, int n, const BitGate& b) {
-  Pass ps;
-  ps.kind = PASS_MFMA;
+// Low bits of a matrix-core pass whose blocks of k qubits target the bit set
+// tm: the tile is [0, L) and the targets above L, k + 7 bits in all, with the
+// smallest such L.  -1 when that L is below 7 (rows shorter than 128
+// amplitudes), which only happens when two blocks share a tile.
+int mfma_low_bits(uint64_t tm, int k, int n) {
+  for (int L = 0; L <= n && L < 64; ++L)
+    if (L + __builtin_popcountll(tm >> L) == k + 7) return L >= 7 ? L : -1;
+  return -1;
+}
+
+uint64_t target_mask(const BitGate& b) {
   uint64_t tm = 0;
   for (int t = 0; t < b.k; ++t) tm |= 1ull << b.tb[t];
-  int L = 0, nonT = 0;
-  while (nonT < 7) {
-    if (!((tm >> L) & 1)) ++nonT;
-    ++L;
-  }
+  return tm;
+}
+
+// One matrix-core pass: block b, and with b2 a second block of the same size
+// on other bits that shares the tile (each block's targets lie among the
+// other's 128 columns).
+void add_mfma_pass(Plan& plan, int n, const BitGate& b, const BitGate* b2 = nullptr) {
+  Pass ps;
+  ps.kind = PASS_MFMA;
+  const uint64_t tm = target_mask(b) | (b2 ? target_mask(*b2) : 0);
+  const int L = mfma_low_bits(tm, b.k, n);
+  if (L < 0) throw std::runtime_error("planner: matrix-core blocks do not fit one tile");
+  std::vector<int> hs;
+  for (uint64_t h = L >= 64 ? 0 : (tm >> L) << L; h; h &= h - 1) hs.push_back(__builtin_ctzll(h));
   PassGeom& g = ps.geom;
   std::memset(&g, 0, sizeof(g));
   g.n = n;
   g.L = L;
-  int h = 0;
-  for (int t = 0; t < b.k; ++t)
-    if (b.tb[t] >= L) ++h;
-  std::vector<int> hs;
-  for (int t = 0; t < b.k; ++t)
-    if (b.tb[t] >= L) hs.push_back(b.tb[t]);
-  std::sort(hs.begin(), hs.end());
-  g.H = h;
-  g.m = L + h;
-  for (int i = 0; i < h; ++i) g.hbits[i] = hs[i];
+  g.H = (int)hs.size();
+  g.m = L + g.H;
+  for (int i = 0; i < g.H; ++i) g.hbits[i] = hs[i];
   g.kern = 0;
-  TileOp op;
-  std::memset(&op, 0, sizeof(op));
-  op.kind = OP_MFMA;
-  op.k = b.k;
-  op.gslot = -1;
-  op.pidx = -1;
-  op.aux = -1;
-  for (int t = 0; t < b.k; ++t) {
-    const int bit = b.tb[t];
-    op.b[t] = bit < L ? bit : L + (int)(std::find(hs.begin(), hs.end(), bit) - hs.begin());
+  for (const BitGate* bp : {&b, b2}) {
+    if (!bp) continue;
+    TileOp op;
+    std::memset(&op, 0, sizeof(op));
+    op.kind = OP_MFMA;
+    op.k = bp->k;
+    op.gslot = -1;
+    op.pidx = -1;
+    op.aux = -1;
+    for (int t = 0; t < bp->k; ++t) {
+      const int bit = bp->tb[t];
+      op.b[t] = bit < L ? bit : L + (int)(std::find(hs.begin(), hs.end(), bit) - hs.begin());
+    }
+    const int dim = 1 << bp->k;
+    op.mat = (int)plan.matpool.size();
+    plan.matpool.insert(plan.matpool.end(), bp->mat.begin(), bp->mat.end());
+    std::vector<cd> inv = dagger(bp->mat, dim);
+    plan.matpool.insert(plan.matpool.end(), inv.begin(), inv.end());
+    ps.ops.push_back(op);
   }
-  const int dim = 1 << b.k;
-  op.mat = (int)plan.matpool.size();
-  plan.matpool.insert(plan.matpool.end(), b.mat.begin(), b.mat.end());
-  std::vector<cd> inv = dagger(b.mat, dim);
-  plan.matpool.insert(plan.matpool.end(), inv.begin(), inv.end());
-  ps.ops.push_back(op);
   plan.passes.push_back(ps);
 }
 
@@ -1362,8 +1375,19 @@ Plan plan_tiles(const HostCircuit& C, const TuneOpts& opts, bool dbl, int m, int
           mg = g;
           break;
         }
+      // with a second ready block of the same size on other bits when both fit
+      // one tile (two complex128 blocks of 32 exceed the kernel's registers)
+      int mg2 = -1;
+      if (mg >= 0)
+        for (int g : ready) {
+          if (g == mg || !bg[g].mfma || bg[g].k != bg[mg].k || (dbl && bg[g].k > 4)) continue;
+          if (target_mask(bg[g]) & target_mask(bg[mg])) continue;
+          if (mfma_low_bits(target_mask(bg[g]) | target_mask(bg[mg]), bg[mg].k, n) < 0) continue;
+          mg2 = g;
+          break;
+        }
       if (mg >= 0) {
-        PhasePoly Q = extract_terms(P, n, bg[mg].nmask, false);
+        PhasePoly Q = extract_terms(P, n, bg[mg].nmask | (mg2 >= 0 ? bg[mg2].nmask : 0), false);
         if (!Q.empty) {
           RawOp ro;
           ro.kind = OP_PHASE;
@@ -1390,9 +1414,13 @@ Plan plan_tiles(const HostCircuit& C, const TuneOpts& opts, bool dbl, int m, int
       if (placed == 0 && raw.empty() && mg < 0) throw std::runtime_error("planner: no gate fits a tile");
       close_pass(plan, C, m, L, hsel, raw);
       if (mg >= 0) {
-        add_mfma_pass(plan, n, bg[mg]);
+        add_mfma_pass(plan, n, bg[mg], mg2 >= 0 ? &bg[mg2] : nullptr);
         auto it = ready.find(mg);
         finish(mg, it);
+        if (mg2 >= 0) {
+          it = ready.find(mg2);
+          finish(mg2, it);
+        }
       }
     }
     if (!P.empty) {  // only reachable for an all-diagonal remainder after the loop

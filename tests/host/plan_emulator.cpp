@@ -120,6 +120,18 @@ int main(int argc, char** argv) {
       }
     }
     C.nparams = (int)params.size();
+  } else if (mode == 3) {  // dense 5- and 4-qubit blocks on low, high and spread qubits (matrix cores)
+    const std::vector<std::vector<int>> sets = {
+        {n - 5, n - 4, n - 3, n - 2, n - 1}, {0, 1, 2, 3, 4}, {0, n / 4, n / 2, 3 * n / 4, n - 1},
+        {n - 4, n - 3, n - 2, n - 1},       {0, 1, 2, 3},    {3, n / 3 + 1, 2 * n / 3, n - 3},
+        {1, 2, 3, 4},                        {n - 2, n - 3, n - 4, n - 5}};
+    for (const auto& t : sets) {
+      Gate g;
+      g.k = (int)t.size();
+      for (int i = 0; i < g.k; ++i) g.tq[i] = t[i];
+      g.mat = haar(1 << g.k);
+      C.gates.push_back(g);
+    }
   } else {
     const double r = 1 / std::sqrt(2.0);
     for (int j = 0; j < n; ++j) {
@@ -150,7 +162,10 @@ int main(int argc, char** argv) {
   o.tile_bits = tile_bits;
   o.lane_ops = argc > 5 ? atoi(argv[5]) != 0 : true;
   const bool dbl = argc > 6 && atoi(argv[6]) != 0;  // plan for complex128
+  if (mode == 3) o.use_mfma = 1;
   const Plan p = plan_circuit(C, o, dbl);
+  int fused = 0;
+  for (const Pass& ps : p.passes) fused += ps.kind == PASS_MFMA && ps.ops.size() == 2;
 
   std::vector<Z> psi0(1ull << n);
   for (auto& v : psi0) v = Z(N01(rng), N01(rng));
@@ -234,8 +249,8 @@ int main(int argc, char** argv) {
     }
     double err = 0;
     for (size_t i = 0; i < psi.size(); ++i) err = std::max(err, std::abs(psi[i] - ref[i]));
-    std::printf("%s n=%d tile_bits=%d seed=%d mode=%d passes=%zu lane_ops=%d max_err=%.3e\n", form ? "two-state" : "one-state",
-                n, tile_bits, seed, mode, p.passes.size(), lane_ops, err);
+    std::printf("%s n=%d tile_bits=%d seed=%d mode=%d passes=%zu lane_ops=%d mfma_fused=%d max_err=%.3e\n",
+                form ? "two-state" : "one-state", n, tile_bits, seed, mode, p.passes.size(), lane_ops, fused, err);
     if (!(err < 1e-9)) return 1;
   }
   return 0;

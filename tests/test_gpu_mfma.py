@@ -76,6 +76,55 @@ def test_mfma_low_and_high_targets(api):
         assert maxabs(st.download(), ocirc.run(n, spec, oracle_input(psi0, dt))) < TOL[dt]
 
 
+def fused_pairs(n, seed):
+    # consecutive blocks on disjoint bits: a 5-qubit low/high pair, a spread
+    # block, a 4-qubit low/high pair, a spread block, another 4-qubit pair
+    rng = np.random.default_rng(seed)
+    sets = [tuple(range(n - 5, n)), tuple(range(5)), (0, n // 4, n // 2, 3 * n // 4, n - 1),
+            tuple(range(n - 4, n)), tuple(range(4)), (3, n // 3 + 1, 2 * n // 3, n - 3),
+            (1, 2, 3, 4), (n - 2, n - 3, n - 4, n - 5)]
+    return [qsynth.gate("MAT", t, mat=qsynth.haar_unitary(1 << len(t), rng)) for t in sets]
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("n", [12, 16, 20])
+def test_mfma_fused_pairs_vs_oracle(api, dt, n):
+    # two ready blocks of one size on disjoint bits that fit one tile share a
+    # pass (5-qubit pairs only in complex64)
+    banner("mfma fused pairs", dt, n)
+    spec = fused_pairs(n, 70 + n)
+    c = api.Circuit.from_spec(n, spec, use_mfma=1)
+    psi0 = qsynth.random_state(n, 71 + n)
+    st = gpu_state(api, n, dt, psi0)
+    c.run(st)
+    fused = sum(1 for k, _, nops in c.passes() if k == 4 and nops == 2)
+    assert fused == (3 if dt == "c64" else 2)
+    assert maxabs(st.download(), ocirc.run(n, spec, oracle_input(psi0, dt))) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_mfma_fused_pairs_adjoint(api, dt):
+    # the adjoint un-applies both blocks of a fused pass on psi and lambda
+    from oracle import gradients as ograd
+    n = 14
+    banner("mfma fused adjoint", dt)
+    rng = np.random.default_rng(9)
+    spec = [qsynth.gate("RY", (q,), pidx=q) for q in range(n)]
+    spec += fused_pairs(n, 12)
+    spec += [qsynth.gate("RX", (q,), pidx=n + q) for q in range(n)]
+    params = rng.uniform(0, 2 * np.pi, 2 * n)
+    terms = qsynth.random_pauli_sum(n, 8, 2)
+    c = api.Circuit.from_spec(n, spec, use_mfma=1)
+    psi, lam = api.State(n, dt), api.State(n, dt)
+    c.run(psi, params)
+    assert any(k == 4 and nops == 2 for k, _, nops in c.passes())
+    H = api.Observable.pauli_sum(n, terms)
+    e, g = api.adjoint(c.h, params, H.h, psi.h, lam.h, c.nparams)
+    e_ref, g_ref = ograd.adjoint(n, spec, params, terms)
+    tol = 1e-10 if dt == "c128" else 2e-4
+    assert abs(e - e_ref) < tol and np.max(np.abs(g - g_ref)) < tol
+
+
 def test_mfma_adjoint_passes(api):
     # an energy gradient through a circuit with matrix-core blocks
     from oracle import gradients as ograd

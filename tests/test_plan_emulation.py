@@ -28,7 +28,8 @@ def emulator(tmp_path_factory):
 @pytest.mark.parametrize("lanes", [0, 1])
 @pytest.mark.parametrize("n,tile_bits,seed,mode", [
     (15, 0, s, 0) for s in range(1, 9)] + [(14, 12, s, 0) for s in range(1, 9)] + [(15, 13, 2, 0)] +
-    [(n, 12, 5, 1) for n in (12, 13, 14, 15, 16)] + [(n, 12, 5, 2) for n in (12, 13, 14, 16)])
+    [(n, 12, 5, 1) for n in (12, 13, 14, 15, 16)] + [(n, 12, 5, 2) for n in (12, 13, 14, 16)] +
+    [(n, 0, 7, 3) for n in (12, 13, 14, 16)])
 def test_planned_ops_replay_the_circuit(emulator, n, tile_bits, seed, mode, lanes, dbl):
     r = subprocess.run([emulator, str(n), str(tile_bits), str(seed), str(mode), str(lanes), str(dbl)],
                        capture_output=True, text=True)
@@ -48,3 +49,13 @@ def test_no_lane_ops_unless_asked(emulator):
     r = subprocess.run([emulator, "14", "12", "5", "1", "0"], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout
     assert all(line.split("lane_ops=")[1].split()[0] == "0" for line in r.stdout.strip().splitlines())
+
+
+@pytest.mark.parametrize("dbl,expect", [(0, 3), (1, 2)])
+def test_matrix_core_blocks_on_disjoint_bits_share_passes(emulator, dbl, expect):
+    # two ready blocks of the same size whose targets fit one tile run in one
+    # pass: at 16 qubits the 5-qubit low/high pair and two 4-qubit pairs (only
+    # the 4-qubit pairs in complex128)
+    r = subprocess.run([emulator, "16", "0", "7", "3", "0", str(dbl)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout
+    assert all(int(line.split("mfma_fused=")[1].split()[0]) == expect for line in r.stdout.strip().splitlines())
