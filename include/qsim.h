@@ -248,7 +248,10 @@ qs_status qs_sample(const qs_state* s, int32_t m, const int32_t* qubits, int64_t
  * s_k = (k + 1/2) dt / T: RX(-(1 - s_k) dt) on every qubit, the phase
  * exp(-i s_k dt E(x)), RX(-(1 - s_k) dt) again (adjacent RX halves merged).
  * The state is evolved in place from whatever it holds (use set_plus for
- * the ground state of H0).  energy_out (may be NULL) receives <H1> at the end. */
+ * the ground state of H0).  energy_out (may be NULL) receives <H1> at the end.
+ * The pass plans of the Trotter blocks are built at the first run with h1 in
+ * a precision and kept in h1 for later runs (freed by qs_obs_destroy): runs
+ * that share h1 must not overlap (one host thread at a time). */
 qs_status qs_adiabatic_run(qs_state* s, const qs_obs* h1, double T, double dt, int32_t order,
                            double* energy_out);
 

@@ -269,6 +269,12 @@ struct qs_circuit {
   std::vector<int> slot_pidx;
 };
 
+// Trotter block plans of one Ising observable and precision, by block length
+// and whether the closing rotation layer rides the block.
+struct TrotterPlans {
+  std::map<std::pair<int, bool>, std::pair<Plan, std::unique_ptr<DevPlanBuf>>> m;
+};
+
 struct qs_obs {
   int n = 0;
   bool ising = false;
@@ -288,6 +294,9 @@ struct qs_obs {
   std::vector<int> far;  // groups whose flip bits do not fit a tile
   bool dev_ok = false;
   DBuf dflips, dgoff, dterms, dpoly, delo, dtgroups, dtterms;
+  // adiabatic runs with this observable as H1: their Trotter plans (complex64,
+  // complex128), planned and uploaded at the first run and kept for later ones
+  TrotterPlans trotter[2];
   void to_device(hipStream_t s) {
     if (dev_ok) return;
     upload(dflips, flips, s);
@@ -1268,10 +1277,8 @@ int64_t step_count(double T, double dt) {
 // steps share passes (the last pass of a step carries the next step's
 // rotations on its tile bits): up to 16 steps form one block, longer segments
 // replay blocks of 8, and the last block also carries the closing layer.
-// Plans depend only on the block length, so they are cached in `plans`.
-struct TrotterPlans {
-  std::map<std::pair<int, bool>, std::pair<Plan, std::unique_ptr<DevPlanBuf>>> m;
-};
+// Plans depend only on the block length for a given H1 and precision; they
+// are cached on the observable.
 
 void trotter_segment(qs_state* s, const PhasePoly& E, double T, double dt, int64_t k0, int64_t k1, TrotterPlans& tp) {
   const int n = s->n;
@@ -1427,7 +1434,7 @@ qs_status qs_adiabatic_run_callbacks(qs_state* s, const qs_obs* h1, double T, do
     const int64_t K = step_count(T, dt);
     check_callbacks(cb, s);
     const PhasePoly E = ising_poly(s->n, h1->J.data(), h1->h.data());
-    TrotterPlans tp;
+    TrotterPlans& tp = const_cast<qs_obs*>(h1)->trotter[s->dbl() ? 1 : 0];
     const int64_t every = (cb && cb->every > 0) ? cb->every : K;
     int64_t idx = 0;
     for (int64_t k0 = 0; k0 < K; k0 += every) {

@@ -431,6 +431,29 @@ def test_adiabatic_trotter_vs_oracle(api, dt):
     assert abs(e - oad.energy(ref, E)) < (1e-10 if dt == "c128" else 1e-4)
 
 
+def test_adiabatic_plans_kept_on_the_observable(api):
+    # later runs with the same H1 reuse the Trotter plans kept on it: the same
+    # amplitudes bit for bit as with a fresh observable, in both precisions and
+    # across block lengths (12 steps: one block; 40 steps: blocks of 8)
+    n = 9
+    banner("adiabatic plan reuse")
+    J, h = qsynth.ising_couplings(n, 6)
+    E = oobs.ising_energies(J, h)
+    kept = api.Observable.ising(n, J, h)
+    for dt in ("c64", "c128", "c64"):
+        for steps in (12, 40, 12):
+            a = api.State(n, dt)
+            a.set_plus()
+            ea = api.adiabatic_run(a.h, kept.h, steps * 0.05, 0.05)
+            fresh = api.Observable.ising(n, J, h)
+            b = api.State(n, dt)
+            b.set_plus()
+            eb = api.adiabatic_run(b.h, fresh.h, steps * 0.05, 0.05)
+            assert np.array_equal(a.download(), b.download()) and ea == eb
+            ref = oad.trotter(n, E, steps * 0.05, 0.05)
+            assert maxabs(a.download(), ref) < (1e-11 if dt == "c128" else 2e-5)
+
+
 @pytest.mark.parametrize("dt", DTS)
 def test_adiabatic_trotter_staged_blocks(api, dt):
     # register-staged passes, 37 steps = four blocks of 8 shared-pass steps
