@@ -273,6 +273,7 @@ struct qs_circuit {
 // and whether the closing rotation layer rides the block.
 struct TrotterPlans {
   std::map<std::pair<int, bool>, std::pair<Plan, std::unique_ptr<DevPlanBuf>>> m;
+  DBuf ang, scl;  // per-step rotation angles and phase scales of the current segment
 };
 
 struct qs_obs {
@@ -1308,7 +1309,8 @@ void trotter_segment(qs_state* s, const PhasePoly& E, double T, double dt, int64
     ang[j] = a;
   }
   for (int64_t j = 0; j < K; ++j) scl[j] = -sk(k0 + j) * dt;
-  DBuf dang, dscl;
+  DBuf& dang = tp.ang;
+  DBuf& dscl = tp.scl;
   upload(dang, ang, s->stream);
   upload(dscl, scl, s->stream);
   if (nfull > 0) {
@@ -1321,7 +1323,8 @@ void trotter_segment(qs_state* s, const PhasePoly& E, double T, double dt, int64
   auto& last = get(L, true);
   run_passes(*last.second, last.first, dbl, s->ptr, nullptr, dang.as<double>() + (K - L), dscl.as<double>() + (K - L),
              nullptr, s->stream);
-  // dang / dscl are freed when this returns: the passes that read them must be done
+  // the host angle and scale arrays end with this call, and the next segment
+  // rewrites dang / dscl: the copies and the passes that read them must be done
   hipck(hipStreamSynchronize(s->stream), "sync");
 }
 
