@@ -108,6 +108,27 @@ def test_noisy_circuit_vs_dense_oracle(api, dt, n, depth, seed):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_dense_blocks_on_rows_and_columns_share_matrix_core_passes(api, dt):
+    # a 4-qubit gate becomes U on the row bits and conj(U) on the column bits:
+    # two blocks on disjoint bits, which share one matrix-core launch
+    n = 8
+    banner("density mfma pairs", n, dt)
+    rng = np.random.default_rng(21)
+    spec = [qsynth.gate("MAT", (0, 1, 2, 3), mat=qsynth.haar_unitary(16, rng)),
+            qsynth.gate("CH:depolarizing", (2,), theta=0.1),
+            qsynth.gate("MAT", (4, 5, 6, 7), mat=qsynth.haar_unitary(16, rng)),
+            qsynth.gate("MAT", (1, 3, 5, 7), mat=qsynth.haar_unitary(16, rng))]
+    c = api.DensityCircuit.from_spec(n, spec, use_mfma=1)
+    rho = api.DensityMatrix(n, dt)
+    c.run(rho)
+    assert any(k == 4 and nops == 2 for k, _, nops in c.passes())
+    ref = oden.run(n, spec, None, None)
+    assert maxabs(rho.download(), ref) < TOL[dt]
+    assert abs(rho.trace() - 1.0) < 10 * TOL[dt]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_unitary_density_circuit_is_outer_product_of_state(api, dt):
     # no channel: rho(out) = |U psi><U psi| for rho(in) = |psi><psi|, here from
     # a random state (set_pure) through a mixed list of gates and controls
